@@ -1,0 +1,43 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU tests.
+
+Holds none of the method's arithmetic: only random smooth fields and
+population arrays built from a caller-supplied base vector.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def smooth_field(shape, rng: np.random.Generator, nmodes: int = 4) -> np.ndarray:
+    """Sum of ``nmodes`` low Fourier modes per axis with random coefficients,
+    scaled to max |value| = 1."""
+    grids = np.meshgrid(*[np.linspace(0.0, 1.0, s) for s in shape], indexing="ij")
+    out = np.zeros(shape)
+    for _ in range(nmodes):
+        term = rng.normal()
+        for g in grids:
+            k = rng.integers(1, 4)
+            term = term * np.cos(np.pi * k * g + rng.uniform(0, 2 * np.pi))
+        out += term
+    m = np.abs(out).max()
+    return out / m if m > 0 else out
+
+
+def random_populations(shape, base, amp: float, seed: int, noise: float = 1e-3) -> np.ndarray:
+    """[q, *shape] float64: base_i * (1 + amp * smooth_i + noise * white_i)."""
+    rng = np.random.default_rng(seed)
+    base = np.asarray(base, dtype=np.float64)
+    out = np.empty((len(base),) + tuple(shape))
+    for i, b in enumerate(base):
+        out[i] = b * (1.0 + amp * smooth_field(shape, rng) + noise * rng.normal(size=shape))
+    return out
+
+
+def random_scalar_populations(shape, q: int, scale: float, seed: int,
+                              noise: float = 1e-3) -> np.ndarray:
+    """[q, *shape] float64 with values scale/q * (smooth in [-1,1] + noise)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((q,) + tuple(shape))
+    for i in range(q):
+        out[i] = scale / q * (smooth_field(shape, rng) + noise * rng.normal(size=shape))
+    return out

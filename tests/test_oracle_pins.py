@@ -1,0 +1,477 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the
+equilibrium moments and forcing moments printed in Sec. 2.1 (via textbook
+population-space equilibria), the mesh-quality numbers of Sec. 2.3, the
+closed forms of Eqs. (16)-(18), exact solutions (shear and thermal decay
+modes, the conduction limit), exact symmetries, and independent
+re-implementations of the uniform-mesh shift.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.seeded import random_populations, random_scalar_populations
+
+SQ3 = np.sqrt(3.0)
+
+
+def lu(kind, n, a=1.5):
+    """Mesh coordinates in lattice units (first spacing = 1), so that axes of
+    different node counts share one lattice unit."""
+    x = oracle.mesh(kind, n, a)
+    return x / (x[1] - x[0])
+
+
+def textbook_feq(e, w, rho, u):
+    """Second-order Maxwellian equilibrium in population space."""
+    eu = e[:, :len(u)] @ np.asarray(u)
+    uu = float(np.dot(u, u))
+    return w * rho * (1.0 + 3.0 * eu + 4.5 * eu ** 2 - 1.5 * uu)
+
+
+def guo_force(e, w, u, F):
+    """Guo et al. (2002) discrete force term F~_i (population space)."""
+    d = len(u)
+    ee = e[:, :d].astype(float)
+    eu = ee @ np.asarray(u)
+    return w * (3.0 * ((ee - np.asarray(u)) @ np.asarray(F)) + 9.0 * eu * (ee @ np.asarray(F)))
+
+
+# ---------------------------------------------------------------- lattice ---
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_basis_orthogonal_and_weights(dim):
+    e, w, M = oracle.lattice(dim, 0)
+    G = M @ M.T
+    assert np.allclose(G, np.diag(np.diag(G)), atol=1e-12)
+    norms = {2: [9, 36, 36, 6, 12, 6, 12, 4, 4],
+             3: [19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8]}[dim]
+    assert np.allclose(np.diag(G), norms)
+    # weights: normalisation and isotropy with c_s^2 = 1/3
+    assert abs(w.sum() - 1.0) < 1e-15
+    ee = e.astype(float)
+    second = np.einsum("i,ia,ib->ab", w, ee[:, :dim], ee[:, :dim])
+    assert np.allclose(second, np.eye(dim) / 3.0, atol=1e-15)
+    # thermal set
+    eg, _, N = oracle.lattice(dim, 1)
+    Gn = N @ N.T
+    assert np.allclose(Gn, np.diag(np.diag(Gn)), atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_equilibrium_moments_match_paper(dim):
+    """M f^eq(rho,u) of the textbook equilibrium equals the printed m^eq."""
+    e, w, M = oracle.lattice(dim, 0)
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        rho = 1.0 + 0.1 * rng.normal()
+        u = 0.1 * rng.normal(size=dim)
+        m_pop = M @ textbook_feq(e, w, rho, u)
+        assert np.allclose(m_pop, oracle.meq(dim, rho, u), atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_forcing_moments_match_guo(dim):
+    """M F~ of Guo's population-space force equals the oracle's forcing moments."""
+    e, w, M = oracle.lattice(dim, 0)
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        u = 0.1 * rng.normal(size=dim)
+        F = 1e-3 * rng.normal(size=dim)
+        assert np.allclose(M @ guo_force(e, w, u, F), oracle.mforce(dim, u, F), atol=1e-16)
+
+
+def test_printed_d2q9_forcing_typo_is_inconsistent():
+    """The printed last D2Q9 entry u F_x + v F_y disagrees with Guo's force;
+    u F_y + v F_x (the oracle's reading) agrees."""
+    e, w, M = oracle.lattice(2, 0)
+    u, F = np.array([0.03, -0.02]), np.array([1e-3, 2e-3])
+    mf = M @ guo_force(e, w, u, F)
+    assert abs(mf[8] - (u[0] * F[1] + u[1] * F[0])) < 1e-17
+    assert abs(mf[8] - (u[0] * F[0] + u[1] * F[1])) > 1e-6
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_thermal_equilibrium_and_diffusivity(dim):
+    """N g^eq reproduces the printed n^eq; the second moment of g^eq and the
+    flux relaxation rate give back alpha through a_T (Chapman-Enskog)."""
+    q = 5 if dim == 2 else 7
+    eg, _, N = oracle.lattice(dim, 1)
+    x = oracle.mesh("uniform", 16)
+    o = oracle.Oracle([x] * dim, 1e5, 0.71)
+    p = o.params
+    aT = p["aT"]
+    _, Q = o.rates()
+    qj = Q[1]
+    rng = np.random.default_rng(3)
+    T, u = 0.3, 0.05 * rng.normal(size=dim)
+    # population-space equilibrium: rest weight 1 - (q-1+a_T)/q... built
+    # from the moment condition sum_i>0 g = (q-1+a_T) T / q
+    wmov = (q - 1 + aT) / (q * (q - 1))
+    geq = np.full(q, wmov * T) + 0.5 * T * (eg[:, :dim] @ u)
+    geq[0] = T - wmov * T * (q - 1)
+    assert np.allclose(N @ geq, oracle.neq(dim, aT, T, u), atol=1e-15)
+    # c_sT^2 from the second moment of the equilibrium at rest
+    geq0 = np.full(q, wmov * T)
+    geq0[0] = T - wmov * T * (q - 1)
+    cs2 = float(np.sum(geq0 * eg[:, 0] ** 2) / T)
+    alpha_ce = cs2 * (1.0 / qj - 0.5)
+    assert abs(alpha_ce - p["alpha"]) < 1e-14
+    # anti-bounce-back weight is twice the moving equilibrium weight per unit T
+    assert abs(p["omega"] - 2.0 * wmov) < 1e-15
+    # Eqs. (5)-(7): alpha = u_f H / sqrt(Ra Pr), nu = u_f H sqrt(Pr/Ra)
+    assert abs(p["alpha"] - p["uf"] * p["H_lu"] / np.sqrt(1e5 * 0.71)) < 1e-15
+    assert abs(p["nu"] - p["uf"] * p["H_lu"] * np.sqrt(0.71 / 1e5)) < 1e-15
+    # Ma = 0.1 default (Sec. 3): u_f = 0.1 c_s
+    assert abs(p["uf"] - 0.1 / SQ3) < 1e-16
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_collision_structure(dim):
+    """Each moment relaxes at its own rate towards the textbook equilibrium
+    and receives (1 - s/2) of Guo's forcing moment; rho and T are conserved
+    and momentum gains exactly F."""
+    e, w, M = oracle.lattice(dim, 0)
+    eg, _, N = oracle.lattice(dim, 1)
+    x = oracle.mesh("tanh", 12, 1.5)
+    o = oracle.Oracle([x] * dim, 1e6, 0.71)
+    S, Q = o.rates()
+    p = o.params
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        f = w * (1.0 + 0.05 * rng.normal(size=len(w)))
+        g = 0.1 * rng.normal(size=len(eg))
+        fo, go = o.collide_node(f, g)
+        rho, T = f.sum(), g.sum()
+        F = np.zeros(dim)
+        F[1] = rho * p["gbeta"] * (T - p["T0"])
+        u = (e[:, :dim].T @ f + 0.5 * F) / rho
+        m, mo = M @ f, M @ fo
+        meq_pop = M @ textbook_feq(e, w, rho, u)
+        mF = M @ guo_force(e, w, u, F)
+        expect = m - S * (m - meq_pop) + (1.0 - 0.5 * S) * mF
+        assert np.allclose(mo, expect, atol=1e-14)
+        assert abs(fo.sum() - rho) < 1e-14
+        assert np.allclose(e[:, :dim].T @ fo, e[:, :dim].T @ f + F, atol=1e-15)
+        assert abs(go.sum() - T) < 1e-15
+        # g: n+ = n - Q (n - n^eq) with n^eq from the population-space equilibrium
+        q = len(eg)
+        wmov = (q - 1 + p["aT"]) / (q * (q - 1))
+        geq = np.full(q, wmov * T) + 0.5 * T * (eg[:, :dim] @ u)
+        geq[0] = T - wmov * T * (q - 1)
+        n = N @ g
+        assert np.allclose(N @ go, n - Q * (n - N @ geq), atol=1e-15)
+    # relaxation-rate readings: s_nu = 1/(3 nu + 1/2), Lambda = 3/16 pairing
+    snu = 1.0 / (3.0 * p["nu"] + 0.5)
+    assert abs(p["s_nu"] - snu) < 1e-15
+    sq = S[4]
+    assert abs((1 / snu - 0.5) * (1 / sq - 0.5) - 3.0 / 16.0) < 1e-14
+    assert abs(Q[1] - (3.0 - SQ3)) < 1e-15
+
+
+# ------------------------------------------------------------------ meshes ---
+
+def test_mesh_quality_matches_paper():
+    """Sec. 2.3: erf, a = 1.5, 513 nodes: max growth 1.0044, aspect ratio 1.75."""
+    x = oracle.mesh("erf", 513, 1.5)
+    d = np.diff(x)
+    assert round(float((d[1:] / d[:-1]).max()), 4) == 1.0044
+    assert round(float(d.max() / d.min()), 2) == 1.75
+    # ends at 0 and 1, minimum spacing y_1 (Table 1: 1 l.u.)
+    assert x[0] == 0.0 and abs(x[-1] - 1.0) < 1e-15
+    assert abs(d.min() - x[1]) < 1e-18
+
+
+@pytest.mark.parametrize("kind,a", [("uniform", 0), ("erf", 1.5), ("cosine", 0), ("tanh", 1.5)])
+def test_mesh_lattice_units(kind, a):
+    """Table 1: H = (1/y_1 - 1) l.u. for stretched meshes, N l.u. uniform;
+    ghost spacings equal the minimum spacing; midpoint weights tile H."""
+    n = 40
+    x = oracle.mesh(kind, n, a)
+    d = np.diff(x)
+    assert abs(d[0] - d.min()) < 1e-15 and abs(d[-1] - d[0]) < 1e-15
+    o = oracle.Oracle([x, x], 1e6, 0.71)
+    H = o.params["H_lu"]
+    if kind == "uniform":
+        assert abs(H - n) < 1e-12
+    else:
+        assert abs(H - (1.0 / x[1] - 1.0)) < 1e-9 * H
+    V = 0.5 * (x[2:] - x[:-2])
+    assert abs(V.sum() - (1.0 - d[0])) < 1e-14 or kind == "uniform"
+
+
+# -------------------------------------------------------------- Eqs 16-17 ---
+
+def test_wall_derivative_equals_quadratic_fit():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        q = 1.0 + 2.0 * rng.random()
+        phi = rng.normal(size=3)
+        # wall at 0, node 1 at 1/2, node 2 at 1/2 + q  (Delta = 1)
+        pts = np.array([0.0, 0.5, 0.5 + q])
+        c = np.polyfit(pts, phi, 2)
+        d0 = np.polyval(np.polyder(c), 0.0)
+        assert abs(oracle.wall_derivative(0, q, *phi) - d0) < 1e-11
+        # top wall: mirror image
+        assert abs(oracle.wall_derivative(1, q, *phi) + d0) < 1e-11
+    # Eq. (16) is Eq. (17) at q = 1
+    phiw, p1, p2 = 0.3, 0.7, 1.9
+    assert abs(oracle.wall_derivative(0, 1.0, phiw, p1, p2) - (-8 * phiw + 9 * p1 - p2) / 3) < 1e-15
+
+
+def test_lagrange_reproduces_quadratics():
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        xs = np.sort(rng.random(3)) + np.array([0, 0.1, 0.2])
+        c = rng.normal(size=3)
+        xd = xs[0] + (xs[2] - xs[0]) * rng.random()
+        w = oracle.lagrange3(xs, xd, 1e-3)
+        assert abs(w @ np.polyval(c, xs) - np.polyval(c, xd)) < 1e-13
+
+
+# ------------------------------------------------------ streaming property ---
+
+def shift_stream(e, src, wall_rule):
+    """Plain uniform-mesh streaming by array shifts (independent of the
+    oracle's interpolation), with a callback for links that cross a wall."""
+    q = src.shape[0]
+    shape = src.shape[1:]
+    dim = len(shape)
+    out = np.empty_like(src)
+    for p in range(q):
+        ev = e[p, :dim][::-1]           # array axes are (z, y, x)
+        idx = np.indices(shape)
+        srcidx = [idx[k] - ev[k] for k in range(dim)]
+        inside = np.ones(shape, bool)
+        for k in range(dim):
+            inside &= (srcidx[k] >= 0) & (srcidx[k] < shape[k])
+        vals = np.zeros(shape)
+        clipped = [np.clip(srcidx[k], 0, shape[k] - 1) for k in range(dim)]
+        vals[inside] = src[p][tuple(clipped)][inside]
+        out[p] = np.where(inside, vals, wall_rule(p, inside))
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_uniform_mesh_stream_is_exact_shift(dim):
+    """Property (a): on a uniform mesh the interpolated stream reduces
+    bitwise to the standard lattice shift with half-way wall rules."""
+    shape = (7, 9, 11)[:dim][::-1] if dim == 3 else (9, 13)
+    n = list(shape[::-1])
+    coords = [lu("uniform", k) for k in n]
+    o = oracle.Oracle(coords, 1e5, 0.71, Thot=0.7, Tcold=-0.2)
+    e, w, _ = oracle.lattice(dim, 0)
+    eg, _, _ = oracle.lattice(dim, 1)
+    fp = random_populations(shape, w, 0.1, seed=7)
+    gp = random_scalar_populations(shape, len(eg), 0.5, seed=8)
+    o.set_post(fp, gp)
+    o.stream()
+    f, g = o.state()
+    opp_f = [int(np.where((e == -e[p]).all(1))[0][0]) for p in range(len(e))]
+    opp_g = [int(np.where((eg == -eg[p]).all(1))[0][0]) for p in range(len(eg))]
+    omega = o.params["omega"]
+    ef = shift_stream(e, fp, lambda p, inside: fp[opp_f[p]])
+
+    def grule(p, inside):
+        if eg[p, 0] == 1:
+            return -gp[opp_g[p]] + omega * 0.7
+        if eg[p, 0] == -1:
+            return -gp[opp_g[p]] + omega * -0.2
+        return gp[opp_g[p]]
+
+    eg_ = shift_stream(eg, gp, grule)
+    assert np.array_equal(f, ef)
+    assert np.array_equal(g, eg_)
+
+
+@pytest.mark.parametrize("dim,kind", [(2, "tanh"), (2, "cosine"), (3, "erf")])
+def test_quadratic_fields_are_reproduced(dim, kind):
+    """Property (b): with collision switched off, post-collision fields that
+    are per-axis quadratics stream to their exact values at the departure
+    points x - e_i Delta, clamped end stencils included."""
+    n = [13, 10, 8][:dim]
+    coords = [lu(kind, k) for k in n]
+    o = oracle.Oracle(coords, 1e6, 0.71)
+    o.override(collide=False)
+    delta = o.params["delta"]
+    e, _, _ = oracle.lattice(dim, 0)
+    eg, _, _ = oracle.lattice(dim, 1)
+    rng = np.random.default_rng(9)
+    X = np.meshgrid(*[c[1:-1] for c in coords[::-1]], indexing="ij")[::-1]  # x, y, (z)
+
+    def make(q):
+        polys = rng.normal(size=(q, dim, 3))
+
+        def field(p, shift):
+            val = np.ones(X[0].shape)
+            for a in range(dim):
+                val = val * np.polyval(polys[p, a], X[a] - shift[a] * delta)
+            return val
+        return field
+
+    ff, gf = make(len(e)), make(len(eg))
+    fp = np.stack([ff(p, [0] * dim) for p in range(len(e))])
+    gp = np.stack([gf(p, [0] * dim) for p in range(len(eg))])
+    o.set_post(fp, gp)
+    o.stream()
+    f, g = o.state()
+    for arr, field, ev in ((f, ff, e), (g, gf, eg)):
+        for p in range(len(ev)):
+            expect = field(p, ev[p, :dim])
+            # links crossing a wall take the wall rule; compare the rest
+            mask = np.ones(X[0].shape, bool)
+            for a in range(dim):
+                ax = dim - 1 - a
+                sl = [slice(None)] * dim
+                if ev[p, a] == 1:
+                    sl[ax] = 0
+                    mask[tuple(sl)] = False
+                if ev[p, a] == -1:
+                    sl[ax] = -1
+                    mask[tuple(sl)] = False
+            scale = np.abs(expect).max()
+            assert np.abs(arr[p][mask] - expect[mask]).max() <= 1e-12 * scale
+
+
+# --------------------------------------------------------- conservation ---
+
+def test_mass_conserved_on_uniform_mesh():
+    """Property (c), uniform: bounce-back + permutation streaming + mass
+    conserving collision keep sum(rho) to round-off."""
+    x = lu("uniform", 20)
+    y = lu("uniform", 14)
+    o = oracle.Oracle([x, y], 1e6, 0.71)
+    _, w, _ = oracle.lattice(2, 0)
+    f = random_populations((14, 20), w, 0.05, seed=10)
+    g = random_scalar_populations((14, 20), 5, 0.5, seed=11)
+    o.set_state(f, g)
+    m0 = o.stats()["rho_sum"]
+    o.run(200)
+    m1 = o.stats()["rho_sum"]
+    assert abs(m1 - m0) <= 1e-13 * 200 * m0
+
+
+def test_mass_drift_nonuniform_is_small():
+    """Property (c), stretched: the interpolated stream is not exactly
+    conservative (parity unpinned); the drift must stay small and shrink
+    under refinement."""
+    drifts = []
+    for n in (16, 32):
+        x = oracle.mesh("tanh", n, 1.5)
+        o = oracle.Oracle([x, x], 1e5, 0.71)
+        m0 = o.stats()["mass"]
+        o.run(8 * n)
+        drifts.append(abs(o.stats()["mass"] / m0 - 1.0))
+    assert drifts[0] < 1e-3 and drifts[1] < drifts[0]
+
+
+def test_rest_state_is_a_fixed_point():
+    x = oracle.mesh("cosine", 12)
+    o = oracle.Oracle([x, x], 1e6, 0.71, Thot=0.0, Tcold=0.0)
+    f0, g0 = o.state()
+    o.run(50)
+    f1, g1 = o.state()
+    assert np.abs(f1 - f0).max() < 1e-14 and np.abs(g1).max() == 0.0
+
+
+def test_centro_symmetry():
+    """With T0 at the mid temperature the cavity problem is symmetric under
+    point reflection: u(x) = -u(Rx), T(x) = -T(Rx)."""
+    x = oracle.mesh("cosine", 18)
+    o = oracle.Oracle([x, x], 1e5, 0.71, uf=0.1)
+    o.run(300)
+    fl = o.fields()
+    for k in ("ux", "uy", "T"):
+        a = fl[k]
+        assert np.abs(a + a[::-1, ::-1]).max() <= 1e-10 * np.abs(a).max()
+    assert np.abs(fl["T"]).max() > 1e-3 and np.abs(fl["uy"]).max() > 1e-7
+
+
+# --------------------------------------------------------- exact solutions ---
+
+def _decay_rate(series, t):
+    return -np.polyfit(t, np.log(np.abs(series)), 1)[0]
+
+
+@pytest.mark.parametrize("kind,tol", [("uniform", 1e-6), ("tanh", 1e-2)])
+def test_buoyant_parallel_flow(kind, tol):
+    """Tall cavity, conduction regime: the steady state away from the end
+    walls is the exact parallel (Batchelor) flow, T linear in x and
+    v = g beta dT Hx^2/(12 nu) xi (2 xi - 1)(xi - 1).  Pins viscosity,
+    Guo forcing, buoyancy sign and the isothermal walls; starts from rest."""
+    nx, ny = 12, 96
+    cx, cy = lu(kind, nx), lu("uniform", ny)
+    nu, uf, H = 0.075, 0.05, float(ny)
+    o = oracle.Oracle([cx, cy], (uf * H / nu) ** 2, 1.0, uf=uf)
+    p = o.params
+    assert abs(p["nu"] - nu) < 1e-14
+    wall0, wall1 = 0.5 * (cx[0] + cx[1]), 0.5 * (cx[-2] + cx[-1])
+    Hx = wall1 - wall0
+    xi = (cx[1:-1] - wall0) / Hx
+    o.run(int(16 * Hx ** 2 / (np.pi ** 2 * nu)))
+    fl = o.fields()
+    band = slice(ny // 2 - 4, ny // 2 + 4)
+    v, T = fl["uy"][band].mean(0), fl["T"][band].mean(0)
+    v_exact = p["gbeta"] * Hx ** 2 / (12.0 * nu) * xi * (2 * xi - 1) * (xi - 1)
+    assert np.abs(v - v_exact).max() <= tol * np.abs(v_exact).max()
+    assert np.abs(T - (0.5 - xi)).max() < 1e-6
+    # hot fluid rises next to the hot wall (x = 0): v > 0 there
+    assert v[1] > 0
+
+
+@pytest.mark.parametrize("dim,kind,tol", [(2, "uniform", 0.01), (2, "cosine", 0.03),
+                                          (3, "tanh", 0.03)])
+def test_thermal_mode_decays_at_diffusivity(dim, kind, tol):
+    """T = A sin(pi xi) with both side walls at T = 0 (anti-bounce-back) and
+    adiabatic other walls is an exact mode decaying at alpha (pi / H_x)^2."""
+    nx, ny = 24, 6
+    cx = lu(kind, nx)
+    coords = [cx, lu("uniform", ny)] + ([lu("uniform", 5)] if dim == 3 else [])
+    o = oracle.Oracle(coords, 1.0e5, 0.71, uf=0.05, Thot=0.0, Tcold=0.0)
+    o.override(gbeta=0.0)
+    p = o.params
+    delta = p["delta"]
+    eg, _, _ = oracle.lattice(dim, 1)
+    q = len(eg)
+    wall0, wall1 = 0.5 * (cx[0] + cx[1]), 0.5 * (cx[-2] + cx[-1])
+    Hx = (wall1 - wall0) / delta
+    xi = (cx[1:-1] - wall0) / (wall1 - wall0)
+    shape = tuple(len(c) - 2 for c in coords[::-1])
+    T = 0.2 * np.sin(np.pi * xi) * np.ones(shape)
+    wmov = (q - 1 + p["aT"]) / (q * (q - 1))
+    g = np.stack([T * (1 - (q - 1) * wmov)] + [T * wmov] * (q - 1))
+    _, w, _ = oracle.lattice(dim, 0)
+    f = np.stack([np.full(shape, wi) for wi in w])
+    o.set_state(f, g)
+    V = 0.5 * (cx[2:] - cx[:-2])
+    ts, amps = [], []
+    for step in range(8):
+        o.run(60)
+        Tn = o.fields()["T"].reshape(-1, nx).mean(0)
+        amps.append(np.sum(Tn * np.sin(np.pi * xi) * V) / np.sum(np.sin(np.pi * xi) ** 2 * V))
+        ts.append((step + 1) * 60)
+    rate = _decay_rate(np.array(amps[2:]), np.array(ts[2:]))
+    expect = p["alpha"] * (np.pi / Hx) ** 2
+    assert abs(rate / expect - 1.0) < tol, (rate, expect)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "tanh"])
+def test_conduction_limit(kind):
+    """Property (d1): at vanishing Ra the steady temperature is linear between
+    the isothermal walls and Nu_hot = Nu_cold = <Nu> = 1."""
+    n = 14
+    x = oracle.mesh(kind, n, 1.5)
+    Ra, Pr = 1e-6, 0.71     # departures from linear scale with Ra (buoyancy)
+    H = (1.0 / x[1] - 1.0) if kind != "uniform" else float(n)
+    uf = 0.08 * np.sqrt(Ra * Pr) / H                 # alpha_lu = 0.08
+    o = oracle.Oracle([x, x], Ra, Pr, uf=uf)
+    assert abs(o.params["alpha"] - 0.08) < 1e-12
+    o.run(14000)
+    s = o.stats()
+    for k in ("nu_hot", "nu_cold", "nu_vol", "nu_mid"):
+        assert abs(s[k] - 1.0) < 1e-11, (k, s[k])
+    T = o.fields()["T"]
+    wall0, wall1 = 0.5 * (x[0] + x[1]), 0.5 * (x[-2] + x[-1])
+    lin = 0.5 - (x[1:-1] - wall0) / (wall1 - wall0)
+    assert np.abs(T - lin[None, :]).max() < 1e-9
