@@ -1,0 +1,226 @@
+"""Throughput benchmark of the fused ISLBM time step on one MI355X.
+
+Workload (the metric's headline configuration): 2-D side-heated cavity,
+Ra = 1e8, Pr = 0.71, 1024 x 1024 cosine-stretched mesh (x_j = (1 - cos(pi
+j/(N+1)))/2 on both axes), D2Q9 flow + D2Q5 temperature populations, FP32
+structure-of-arrays storage, start at rest, walls +-0.5.  One "step" is one
+fused launch over the whole mesh.  Printed next to it: the same size on a
+uniform mesh (plain-shift kernel), HBM roofline of the dominant kernel, and
+the FP64 CPU oracle timed on the host cores over a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--extra]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E peak
+N_CFG = 1024
+RA, PR = 1e8, 0.71
+BYTES_PER_LU = {2: {"fp32": 112, "fp64": 224, "fp16": 56, "bf16": 56},
+                3: {"fp32": 208, "fp64": 416, "fp16": 104, "bf16": 104}}
+KERNEL_SOURCES = ("paper_2509_01099_amd/csrc/islbm_kernels.hip",
+                  "paper_2509_01099_amd/csrc/islbm_lattice.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_cosine1024_traffic.json")
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stable_uf(H_lu: float, dim: int = 2) -> float:
+    """Largest u_f with a_T <= 1 (non-negative thermal rest weight): the
+    throughput does not depend on u_f, the stability of the run does."""
+    alpha_max = 5.0 / (20.0 * 3 ** 0.5) if dim == 2 else 7.0 / (42.0 * 3 ** 0.5)
+    return min(0.1 / 3 ** 0.5, alpha_max * (RA * PR) ** 0.5 / H_lu)
+
+
+def make_cavity(kind: str, n, storage="fp32", Ra=RA, **opts):
+    import paper_2509_01099_amd as pkg
+
+    sp = [pkg.islbm_mesh_spacing(kind, k, 1.5) for k in n]
+    sp = [s / s[0] for s in sp]
+    H = float(sum(sp[1]) - 0.5 * sp[1][0] - 0.5 * sp[1][-1])
+    uf = opts.pop("u_f", None)
+    if uf is None:
+        uf = stable_uf(H, len(n)) if Ra == RA else 0.0
+    return pkg.Cavity(sp, Ra, PR, storage=storage, u_f=uf, **opts), H, uf
+
+
+def time_run(cav, steps: int, warmup: int):
+    """Warm-up, then exactly `steps` fused launches bracketed by device
+    synchronisation; returns (wall seconds, device-event seconds)."""
+    import torch
+
+    cav.step(warmup)
+    cav.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = cav.time_steps(steps)          # HIP events on the launch stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ms / 1e3
+
+
+def traffic_entry(dig: str):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_digest") != dig:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_target: float = 15.0):
+    """The FP64 oracle, unmodified, on the host cores: a bounded sample of
+    the same workload (1024^2 cosine mesh, Ra 1e8, from rest)."""
+    import numpy as np
+
+    import oracle
+
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    x = oracle.mesh("cosine", N_CFG)
+    x = x / (x[1] - x[0])
+    H = 0.5 * (x[-1] + x[-2]) - 0.5 * (x[0] + x[1])
+    orc = oracle.Oracle([x, x], RA, PR, uf=stable_uf(H))
+    orc.run(1)
+    steps, el = 0, 0.0
+    t0 = time.perf_counter()
+    while el < seconds_target:
+        orc.run(2)
+        steps += 2
+        el = time.perf_counter() - t0
+    mlups = N_CFG * N_CFG * steps / el / 1e6
+    del np
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the 1024^2 cosine 2-D cavity (Ra 1e8, FP64) in "
+                      f"{el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--extra", action="store_true",
+                    help="also time 4096^2 2-D and 256^3 3-D meshes")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run of the headline kernel only, plus a 1 GiB copy for "
+                         "counter calibration (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        return 2
+    import torch
+
+    import paper_2509_01099_amd as pkg
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    pkg.load()
+    n = (N_CFG, N_CFG)
+    nodes = N_CFG * N_CFG
+
+    if args.profile:
+        cav, H, uf = make_cavity("cosine", n)
+        wall, dev = time_run(cav, args.steps, args.warmup)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "steps": args.steps,
+                          "mlups": nodes * args.steps / dev / 1e6,
+                          "copy_bytes": 1 << 30}))
+        return 0
+
+    # headline: non-uniform (cosine) mesh
+    cav, H, uf = make_cavity("cosine", n)
+    wall, dev = time_run(cav, args.steps, args.warmup)
+    st = cav.stats(allow_nonfinite=True)
+    cav.close()
+    mlups = nodes * args.steps / wall / 1e6
+    per_launch = dev / args.steps
+    bpl = BYTES_PER_LU[2]["fp32"] * nodes
+    achieved = bpl / per_launch / 1e9
+    dig = kernel_digest()
+    traffic = traffic_entry(dig)
+
+    # same size, uniform mesh (plain-shift kernel)
+    ucav, uH, uuf = make_cavity("uniform", n)
+    uwall, udev = time_run(ucav, args.steps, args.warmup)
+    ucav.close()
+    umlups = nodes * args.steps / uwall / 1e6
+
+    extra = []
+    if args.extra:
+        for kind, shape, storage, steps in (("cosine", (4096, 4096), "fp32", 2000),
+                                            ("uniform", (4096, 4096), "fp32", 2000),
+                                            ("tanh", (256, 256, 256), "fp32", 1000),
+                                            ("uniform", (256, 256, 256), "fp32", 1000)):
+            c, h, u = make_cavity(kind, shape, storage=storage,
+                                  Ra=1e7 if len(shape) == 3 else RA,
+                                  **({"u_f": 0.0} if len(shape) == 3 else {}))
+            w, d = time_run(c, steps, 50)
+            c.close()
+            nn = 1
+            for k in shape:
+                nn *= k
+            extra.append({"mesh": kind, "shape": list(shape), "storage": storage,
+                          "mlups": round(nn * steps / w / 1e6, 1),
+                          "achieved_GBs": round(BYTES_PER_LU[len(shape)][storage] * nn /
+                                                (d / steps) / 1e9, 1)})
+
+    cpu = None if args.no_cpu else cpu_baseline()
+    out = {
+        "metric": "MLUPS (non-uniform 1024^2 cosine mesh) with % HBM roofline; uniform mesh "
+                  "of the same size alongside",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (cavity started at rest; no external data)",
+        "config": {"workload": "2-D side-heated cavity, Ra=1e8, Pr=0.71, 1024x1024 "
+                               "cosine-stretched mesh, D2Q9+D2Q5 MRT, FP32 SoA populations",
+                   "u_f": uf, "H_lu": H, "nodes": nodes,
+                   "wctpdt_s": round(wall / args.steps * H / uf, 3),
+                   "nonfinite_nodes": st["nonfinite"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "step_kernel<2,Tile<64,16,1,4>,float>",
+                     "bytes_per_launch": bpl, "avg_launch_us": round(per_launch * 1e6, 3)},
+        "uniform": {"value": round(umlups, 1), "unit": "MLUPS",
+                    "nonuniform_over_uniform": round(mlups / umlups, 4),
+                    "achieved_GBs": round(bpl / (udev / args.steps) / 1e9, 1)},
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        out["extra"] = extra
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -155,6 +155,7 @@ class Oracle:
                  Thot: float = 0.5, Tcold: float = -0.5):
         lib = _load()
         self.dim = len(coords)
+        self.Ra, self.Pr = Ra, Pr
         self.coords = [_f64(c) for c in coords]
         self.n = [len(c) - 2 for c in self.coords]
         n3 = (C.c_int * 3)(*(self.n + [1] * (3 - self.dim)))

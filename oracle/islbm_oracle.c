@@ -323,10 +323,13 @@ oracle* oracle_create(int dim, const int* n, const double* x0, const double* x1,
    * both ends equal it and no interior spacing is smaller. */
   for (int a = 0; a < dim; ++a) {
     int na = o->n[a];
+    /* differences of coordinates carry the rounding of their magnitude */
+    double tol = 1e-12 * o->delta +
+                 16.0 * 2.220446049250313e-16 * (fabs(o->x[a][0]) + fabs(o->x[a][na + 1]));
     double d0 = o->x[a][1] - o->x[a][0], d1 = o->x[a][na + 1] - o->x[a][na];
-    int bad = fabs(d0 - o->delta) > 1e-12 * o->delta || fabs(d1 - o->delta) > 1e-12 * o->delta;
+    int bad = fabs(d0 - o->delta) > tol || fabs(d1 - o->delta) > tol;
     for (int j = 0; j <= na; ++j)
-      if (o->x[a][j + 1] - o->x[a][j] < o->delta * (1.0 - 1e-12)) bad = 1;
+      if (o->x[a][j + 1] - o->x[a][j] < o->delta - tol) bad = 1;
     if (bad || na < 3) { oracle_destroy(o); return NULL; }
   }
   o->H_lu = o->heff[1] / o->delta;     /* Table 1: characteristic length */

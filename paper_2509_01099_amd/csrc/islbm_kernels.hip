@@ -1,0 +1,893 @@
+// HIP kernels of the ISLBM time step for gfx950 (MI355X).
+//
+// One launch of step_kernel advances every fluid node by one time step
+// (Sec. 2.1-2.3): the post-collision populations of the previous step are
+// pull-streamed by tensor-product quadratic interpolation at the departure
+// points x - e_i dt (Sec. 2.2; weights precomputed per axis on the host), the
+// half-way bounce-back / anti-bounce-back rules replace links that leave the
+// fluid (Sec. 2.3), then the MRT collision of f and g runs in registers and
+// the new post-collision populations are stored.  Optionally the same launch
+// accumulates the Nusselt / Reynolds / mass reductions in FP64.
+//
+// Memory design: structure-of-arrays planes [pop][z][y][x] with a padded row
+// pitch; every workgroup stages a TX x TY x TZ tile of each moving population
+// plus the halo that population's stencil needs (only along the axes it is
+// shifted on) into LDS with coalesced row loads, so every interpolation tap
+// is an LDS read.  Workgroups are remapped so that consecutive tiles land on
+// the same XCD (blocks are dealt round-robin over the 8 XCDs), which keeps
+// halo re-reads inside one L2.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "islbm_lattice.hpp"
+#include "islbm_launch.hpp"
+
+namespace islbm {
+
+// ---------------------------------------------------------------------------
+// Storage conversion
+// ---------------------------------------------------------------------------
+template <typename S>
+struct Store;
+template <>
+struct Store<float> {
+  using R = float;
+  __device__ static float ld(const float* p) { return *p; }
+  __device__ static void st(float* p, float v) { *p = v; }
+};
+template <>
+struct Store<double> {
+  using R = double;
+  __device__ static double ld(const double* p) { return *p; }
+  __device__ static void st(double* p, double v) { *p = v; }
+};
+template <>
+struct Store<__half> {
+  using R = float;
+  __device__ static float ld(const __half* p) { return __half2float(*p); }
+  __device__ static void st(__half* p, float v) { *p = __float2half_rn(v); }
+};
+template <>
+struct Store<__hip_bfloat16> {
+  using R = float;
+  __device__ static float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+  __device__ static void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+};
+
+template <typename R>
+struct KArgs {
+  int n[3];
+  int pitch;
+  long long plane;
+  int tiles[3];
+  int nblocks;
+  Rates<R> k;
+  R omega, Thot, Tcold;
+  int collide;
+  const R* wtab[3];
+  // reductions
+  double* partials;
+  const double* red;
+  long long red_vol[3], red_mw[3], red_chot, red_ccold, red_cmv, red_cmd;
+  double inv_uf, inv_dT, T0;
+};
+
+template <typename R>
+static KArgs<R> make_args(const DevState& s) {
+  KArgs<R> a{};
+  for (int i = 0; i < 3; ++i) a.n[i] = s.n[i];
+  a.pitch = s.pitch;
+  a.plane = s.plane;
+  a.k.s_e = R(s.s_e);
+  a.k.s_eps = R(s.s_eps);
+  a.k.s_q = R(s.s_q);
+  a.k.s_nu = R(s.s_nu);
+  a.k.s_pi = R(s.s_pi);
+  a.k.s_m = R(s.s_m);
+  a.k.q_j = R(s.q_j);
+  a.k.q_e = R(s.q_e);
+  a.k.q_nu = R(s.q_nu);
+  a.k.aT = R(s.aT);
+  a.k.gbeta = R(s.gbeta);
+  a.k.T0 = R(s.T0);
+  a.omega = R(s.omega);
+  a.Thot = R(s.Thot);
+  a.Tcold = R(s.Tcold);
+  a.collide = s.collide;
+  for (int i = 0; i < 3; ++i) a.wtab[i] = static_cast<const R*>(s.wtab[i]);
+  a.red = s.red;
+  for (int i = 0; i < 3; ++i) {
+    a.red_vol[i] = s.red_vol[i];
+    a.red_mw[i] = s.red_mw[i];
+  }
+  a.red_chot = s.red_chot;
+  a.red_ccold = s.red_ccold;
+  a.red_cmv = s.red_cmv;
+  a.red_cmd = s.red_cmd;
+  a.inv_uf = s.inv_uf;
+  a.inv_dT = s.inv_dT;
+  a.T0 = s.T0;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry and LDS slots (one per moving population)
+// ---------------------------------------------------------------------------
+template <int TX_, int TY_, int TZ_, int NR_>
+struct Tile {
+  static constexpr int TX = TX_, TY = TY_, TZ = TZ_, NR = NR_;
+  static constexpr int ROWS = TY * TZ;       // (y,z) rows of a tile
+  static constexpr int RS = ROWS / NR;       // rows covered by one pass of the block
+  static constexpr int NT = TX * RS;         // threads per block
+  static_assert(ROWS % NR == 0, "rows per thread must divide the tile");
+  __host__ __device__ static constexpr int ext(int a) { return a == 0 ? TX : (a == 1 ? TY : TZ); }
+};
+
+template <int D, class T>
+struct Slots {
+  using LF = typename Pair<D>::F;
+  using LG = typename Pair<D>::G;
+  static constexpr int NF = LF::Q - 1, NG = LG::Q - 1, N = NF + NG;
+  __host__ __device__ static constexpr bool isg(int s) { return s >= NF; }
+  __host__ __device__ static constexpr int pop(int s) { return s < NF ? s + 1 : s - NF + 1; }
+  __host__ __device__ static constexpr int e(int s, int a) {
+    return isg(s) ? LG::e(pop(s), a) : LF::e(pop(s), a);
+  }
+  __host__ __device__ static constexpr int ext(int s, int a) { return T::ext(a) + (e(s, a) != 0 ? 2 : 0); }
+  __host__ __device__ static constexpr int size(int s) { return ext(s, 0) * ext(s, 1) * ext(s, 2); }
+  __host__ __device__ static constexpr int off(int s) {
+    int o = 0;
+    for (int k = 0; k < s; ++k) o += size(k);
+    return o;
+  }
+  // slot of the opposite population (same set)
+  __host__ __device__ static constexpr int opps(int s) {
+    return isg(s) ? NF + opp<LG>(pop(s)) - 1 : opp<LF>(pop(s)) - 1;
+  }
+  static constexpr int total = off(N);
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Geometry of the block's tile: tile origin t0 and halo origin lo per axis.
+struct TileOrigin {
+  int t0[3];
+  int lo[3];
+};
+
+template <class T>
+__device__ __forceinline__ TileOrigin tile_origin(const int* n, const int* tiles, int nblocks) {
+  // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of tiles so that neighbouring tiles share its L2.
+  const int b = blockIdx.x;
+  const int xcd = b & 7, loc = b >> 3;
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  const int lb = xcd * per + (xcd < rem ? xcd : rem) + loc;
+  const int bx = lb % tiles[0];
+  const int byz = lb / tiles[0];
+  const int by = byz % tiles[1];
+  const int bz = byz / tiles[1];
+  TileOrigin o;
+  o.t0[0] = bx * T::TX;
+  o.t0[1] = by * T::TY;
+  o.t0[2] = bz * T::TZ;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o.lo[a] = n[a] >= 3 ? clampi(o.t0[a] - 1, 0, n[a] - 3) : o.t0[a];
+  return o;
+}
+
+// Stage one slot's tile (+ halo along its shifted axes) into LDS.
+template <int D, class T, int s, typename S, typename R>
+__device__ __forceinline__ void load_slot(R* lds, const S* __restrict__ fin, const S* __restrict__ gin,
+                                          const KArgs<R>& a, const TileOrigin& o) {
+  using SL = Slots<D, T>;
+  constexpr int W = SL::ext(s, 0), H = SL::ext(s, 1), V = SL::size(s);
+  const S* src = (SL::isg(s) ? gin : fin) + (long long)SL::pop(s) * a.plane;
+  const int ox = SL::e(s, 0) ? o.lo[0] : o.t0[0];
+  const int oy = SL::e(s, 1) ? o.lo[1] : o.t0[1];
+  const int oz = SL::e(s, 2) ? o.lo[2] : o.t0[2];
+  R* dst = lds + SL::off(s);
+  for (int idx = threadIdx.x; idx < V; idx += T::NT) {
+    const int lz = idx / (W * H);
+    const int rem = idx - lz * (W * H);
+    const int ly = rem / W;
+    const int lx = rem - ly * W;
+    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+    R v = R(0);
+    if (gx < a.n[0] && gy < a.n[1] && gz < a.n[2])
+      v = Store<S>::ld(src + ((long long)gz * a.n[1] + gy) * a.pitch + gx);
+    dst[idx] = v;
+  }
+}
+
+template <int D, class T, typename S, typename R, int... SS>
+__device__ __forceinline__ void load_all(R* lds, const S* fin, const S* gin, const KArgs<R>& a,
+                                         const TileOrigin& o, std::integer_sequence<int, SS...>) {
+  (load_slot<D, T, SS, S, R>(lds, fin, gin, a, o), ...);
+}
+
+// Per-node geometry used by the pulls.
+template <typename R>
+struct NodeGeo {
+  int g[3];       // global node
+  int own[3];     // own node in an unshifted frame (g - t0)
+  int ownh[3];    // own node in a shifted frame (g - lo)
+  int base[3];    // clamped stencil base in the shifted frame
+  R wp[3][3];     // weights, direction +1, per axis
+  R wm[3][3];     // weights, direction -1, per axis
+};
+
+template <int D, class T, int s, bool UNI, typename R>
+__device__ __forceinline__ R pull_slot(const R* lds, const NodeGeo<R>& q, const KArgs<R>& a) {
+  using SL = Slots<D, T>;
+  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
+  constexpr int W = SL::ext(s, 0), H = SL::ext(s, 1);
+  constexpr int sy = W, sz = W * H;
+  const R* L = lds + SL::off(s);
+  // wall link: the departure point lies beyond a wall on some axis
+  const bool wall = (ex == 1 && q.g[0] == 0) || (ex == -1 && q.g[0] == a.n[0] - 1) ||
+                    (ey == 1 && q.g[1] == 0) || (ey == -1 && q.g[1] == a.n[1] - 1) ||
+                    (ez == 1 && q.g[2] == 0) || (ez == -1 && q.g[2] == a.n[2] - 1);
+  if (wall) {
+    constexpr int so = SL::opps(s);
+    const R* Lo = lds + SL::off(so);
+    const int ix = ex ? q.ownh[0] : q.own[0];
+    const int iy = ey ? q.ownh[1] : q.own[1];
+    const int iz = ez ? q.ownh[2] : q.own[2];
+    const R back = Lo[ix + iy * sy + iz * sz];
+    if constexpr (SL::isg(s) && ex != 0) {
+      // anti-bounce-back on the isothermal x walls
+      const R Tw = (ex == 1) ? a.Thot : a.Tcold;
+      return -back + a.omega * Tw;
+    } else {
+      return back;  // bounce-back (no-slip, adiabatic)
+    }
+  }
+  if constexpr (UNI) {
+    const int ix = ex ? q.ownh[0] - ex : q.own[0];
+    const int iy = ey ? q.ownh[1] - ey : q.own[1];
+    const int iz = ez ? q.ownh[2] - ez : q.own[2];
+    return L[ix + iy * sy + iz * sz];
+  } else {
+    const int ix = ex ? q.base[0] : q.own[0];
+    const int iy = ey ? q.base[1] : q.own[1];
+    const int iz = ez ? q.base[2] : q.own[2];
+    const R* P = L + ix + iy * sy + iz * sz;
+    const R* wx = ex > 0 ? q.wp[0] : q.wm[0];
+    const R* wy = ey > 0 ? q.wp[1] : q.wm[1];
+    const R* wz = ez > 0 ? q.wp[2] : q.wm[2];
+    constexpr int nsh = (ex != 0) + (ey != 0) + (ez != 0);
+    if constexpr (nsh == 1) {
+      constexpr int st = ex ? 1 : (ey ? sy : sz);
+      const R* w = ex ? wx : (ey ? wy : wz);
+      return w[0] * P[0] + w[1] * P[st] + w[2] * P[2 * st];
+    } else {
+      // two shifted axes: first along the inner axis (virtual nodes), then
+      // along the outer one (Fig. 1 two-stage construction)
+      constexpr int s1 = ex ? 1 : sy;
+      constexpr int s2 = ez ? sz : sy;
+      const R* w1 = ex ? wx : wy;
+      const R* w2 = ez ? wz : wy;
+      R acc = R(0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const R* Pb = P + b * s2;
+        const R v = w1[0] * Pb[0] + w1[1] * Pb[s1] + w1[2] * Pb[2 * s1];
+        acc = b == 0 ? w2[0] * v : acc + w2[b] * v;
+      }
+      return acc;
+    }
+  }
+}
+
+template <int D, class T, bool UNI, typename R, int... SS>
+__device__ __forceinline__ void pull_all(const R* lds, const NodeGeo<R>& q, const KArgs<R>& a, R* d,
+                                         R* g, std::integer_sequence<int, SS...>) {
+  using SL = Slots<D, T>;
+  ((SL::isg(SS) ? (g[SL::pop(SS)] = pull_slot<D, T, SS, UNI>(lds, q, a))
+                : (d[SL::pop(SS)] = pull_slot<D, T, SS, UNI>(lds, q, a))),
+   ...);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: per-thread FP64 accumulators, wave shuffles, one partial record
+// per workgroup.
+// ---------------------------------------------------------------------------
+struct RedAcc {
+  double v[kRedSlots];
+};
+
+__device__ __forceinline__ void red_init(RedAcc& r) {
+#pragma unroll
+  for (int i = 0; i < kRedSlots; ++i) r.v[i] = 0.0;
+}
+
+template <typename R>
+__device__ __forceinline__ void red_node(RedAcc& r, const KArgs<R>& a, const int* g, const Macro<R>& m) {
+  const double* red = a.red;
+  const double A = red[a.red_vol[1] + g[1]] * red[a.red_vol[2] + g[2]];
+  const double W = red[a.red_vol[0] + g[0]] * A;
+  const double Mw = red[a.red_mw[0] + g[0]] * red[a.red_mw[1] + g[1]] * red[a.red_mw[2] + g[2]];
+  const double rho = double(m.rho);
+  const double us = double(m.u[0]) * a.inv_uf, vs = double(m.u[1]) * a.inv_uf,
+               ws = double(m.u[2]) * a.inv_uf;
+  const double Ts = (double(m.T) - a.T0) * a.inv_dT;
+  r.v[0] += W * us * Ts;
+  r.v[1] += W * sqrt(us * us + vs * vs + ws * ws);
+  r.v[2] += W * sqrt(us * us + vs * vs);
+  r.v[3] += Mw * rho;
+  r.v[4] += rho;
+  r.v[5] += A * red[a.red_chot + g[0]] * Ts;
+  r.v[6] += A * red[a.red_ccold + g[0]] * Ts;
+  r.v[7] += A * (red[a.red_cmv + g[0]] * us * Ts + red[a.red_cmd + g[0]] * Ts);
+  r.v[8] = fmax(r.v[8], fabs(us));
+  r.v[9] = fmax(r.v[9], fabs(vs));
+  r.v[10] = fmax(r.v[10], fabs(ws));
+  const bool bad = !(isfinite(rho) && isfinite(us) && isfinite(vs) && isfinite(ws) && isfinite(Ts));
+  r.v[11] += bad ? 1.0 : 0.0;
+}
+
+template <int NT>
+__device__ __forceinline__ void red_block(RedAcc& r, double* out) {
+  constexpr int NW = NT / 64;
+  __shared__ double sh[NW][kRedSlots];
+#pragma unroll
+  for (int i = 0; i < kRedSlots; ++i) {
+    double v = r.v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off, 64);
+      v = (i >= 8 && i <= 10) ? fmax(v, o) : v + o;
+    }
+    r.v[i] = v;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < kRedSlots; ++i) sh[wid][i] = r.v[i];
+  __syncthreads();
+  if (threadIdx.x < kRedSlots) {
+    const int i = threadIdx.x;
+    double v = sh[0][i];
+    for (int w = 1; w < NW; ++w) v = (i >= 8 && i <= 10) ? fmax(v, sh[w][i]) : v + sh[w][i];
+    out[i] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fused time step
+// ---------------------------------------------------------------------------
+template <int D, class T, typename S, bool UNI, bool REDUCE, bool COLLIDE>
+__global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, const S* __restrict__ gin,
+                                                     S* __restrict__ fout, S* __restrict__ gout,
+                                                     KArgs<typename Store<S>::R> a) {
+  using R = typename Store<S>::R;
+  using SL = Slots<D, T>;
+  using LF = typename SL::LF;
+  using LG = typename SL::LG;
+  __shared__ R lds[SL::total];
+
+  const TileOrigin o = tile_origin<T>(a.n, a.tiles, a.nblocks);
+  load_all<D, T, S, R>(lds, fin, gin, a, o, std::make_integer_sequence<int, SL::N>{});
+
+  const int lx = threadIdx.x % T::TX;
+  const int r0 = threadIdx.x / T::TX;
+  NodeGeo<R> q;
+  q.g[0] = o.t0[0] + lx;
+  q.own[0] = lx;
+  q.ownh[0] = q.g[0] - o.lo[0];
+  const bool xin = q.g[0] < a.n[0];
+  // x-axis weights are shared by every node of this thread
+  if (!UNI && xin) {
+    q.base[0] = clampi(q.g[0] - 1, 0, a.n[0] - 3) - o.lo[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q.wp[0][c] = a.wtab[0][(long long)q.g[0] * 4 + c];
+      q.wm[0][c] = a.wtab[0][((long long)a.n[0] + q.g[0]) * 4 + c];
+    }
+  }
+  // rest populations of this thread's nodes (issued before the barrier)
+  R rest_f[T::NR], rest_g[T::NR];
+#pragma unroll
+  for (int k = 0; k < T::NR; ++k) {
+    const int row = r0 + k * T::RS;
+    const int gy = o.t0[1] + row % T::TY, gz = o.t0[2] + row / T::TY;
+    rest_f[k] = R(0);
+    rest_g[k] = R(0);
+    if (xin && gy < a.n[1] && gz < a.n[2]) {
+      const long long c = ((long long)gz * a.n[1] + gy) * a.pitch + q.g[0];
+      rest_f[k] = Store<S>::ld(fin + c);
+      rest_g[k] = Store<S>::ld(gin + c);
+    }
+  }
+  __syncthreads();
+
+  RedAcc acc;
+  if constexpr (REDUCE) red_init(acc);
+
+#pragma unroll 1
+  for (int k = 0; k < T::NR; ++k) {
+    const int row = r0 + k * T::RS;
+    const int ly = row % T::TY, lz = row / T::TY;
+    q.g[1] = o.t0[1] + ly;
+    q.g[2] = o.t0[2] + lz;
+    if (!xin || q.g[1] >= a.n[1] || q.g[2] >= a.n[2]) continue;
+    q.own[1] = ly;
+    q.own[2] = lz;
+    q.ownh[1] = q.g[1] - o.lo[1];
+    q.ownh[2] = q.g[2] - o.lo[2];
+    if constexpr (!UNI) {
+#pragma unroll
+      for (int ax = 1; ax < D; ++ax) {
+        q.base[ax] = clampi(q.g[ax] - 1, 0, a.n[ax] - 3) - o.lo[ax];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          q.wp[ax][c] = a.wtab[ax][(long long)q.g[ax] * 4 + c];
+          q.wm[ax][c] = a.wtab[ax][((long long)a.n[ax] + q.g[ax]) * 4 + c];
+        }
+      }
+    }
+    R d[LF::Q], g[LG::Q];
+    d[0] = rest_f[k];
+    g[0] = rest_g[k];
+    pull_all<D, T, UNI>(lds, q, a, d, g, std::make_integer_sequence<int, SL::N>{});
+
+    Macro<R> m;
+    if constexpr (COLLIDE) {
+      collide<D>(d, g, a.k, m);
+      if constexpr (REDUCE) red_node(acc, a, q.g, m);
+    } else {
+      if constexpr (REDUCE) {
+        // stream-only: the statistics describe the streamed (pre-collision) state
+        macro_post<D>(d, g, a.k, m);
+        red_node(acc, a, q.g, m);
+      }
+    }
+    const long long c = ((long long)q.g[2] * a.n[1] + q.g[1]) * a.pitch + q.g[0];
+#pragma unroll
+    for (int i = 0; i < LF::Q; ++i) Store<S>::st(fout + (long long)i * a.plane + c, d[i]);
+#pragma unroll
+    for (int i = 0; i < LG::Q; ++i) Store<S>::st(gout + (long long)i * a.plane + c, g[i]);
+  }
+  if constexpr (REDUCE) {
+    const int lb = blockIdx.x;
+    red_block<T::NT>(acc, a.partials + (long long)lb * kRedSlots);
+  }
+}
+
+// Tile shapes per lattice and arithmetic width.
+template <int D, typename R>
+struct TileFor;
+template <>
+struct TileFor<2, float> {
+  using T = Tile<64, 16, 1, 4>;
+};
+template <>
+struct TileFor<2, double> {
+  using T = Tile<64, 8, 1, 2>;
+};
+template <>
+struct TileFor<3, float> {
+  using T = Tile<32, 4, 4, 2>;
+};
+template <>
+struct TileFor<3, double> {
+  using T = Tile<16, 4, 4, 1>;
+};
+
+template <int D, typename S>
+static void grid_of(const DevState& s, KArgs<typename Store<S>::R>& a, int& nb) {
+  using T = typename TileFor<D, typename Store<S>::R>::T;
+  a.tiles[0] = (s.n[0] + T::TX - 1) / T::TX;
+  a.tiles[1] = (s.n[1] + T::TY - 1) / T::TY;
+  a.tiles[2] = (s.n[2] + T::TZ - 1) / T::TZ;
+  nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
+  a.nblocks = nb;
+}
+
+template <int D, typename S, bool UNI, bool RED, bool COL>
+static hipError_t launch_step_t(const DevState& s, const void* fin, const void* gin, void* fout,
+                                void* gout, double* partials, hipStream_t st) {
+  using R = typename Store<S>::R;
+  using T = typename TileFor<D, R>::T;
+  KArgs<R> a = make_args<R>(s);
+  int nb = 0;
+  grid_of<D, S>(s, a, nb);
+  a.partials = partials;
+  hipLaunchKernelGGL((step_kernel<D, T, S, UNI, RED, COL>), dim3(nb), dim3(T::NT), 0, st,
+                     static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
+                     static_cast<S*>(gout), a);
+  return hipGetLastError();
+}
+
+template <int D, typename S>
+static hipError_t dispatch_step(const DevState& s, const void* fin, const void* gin, void* fout,
+                                void* gout, bool reduce, double* partials, hipStream_t st) {
+  const bool uni = s.uniform != 0, col = s.collide != 0;
+  if (col) {
+    if (uni)
+      return reduce ? launch_step_t<D, S, true, true, true>(s, fin, gin, fout, gout, partials, st)
+                    : launch_step_t<D, S, true, false, true>(s, fin, gin, fout, gout, partials, st);
+    return reduce ? launch_step_t<D, S, false, true, true>(s, fin, gin, fout, gout, partials, st)
+                  : launch_step_t<D, S, false, false, true>(s, fin, gin, fout, gout, partials, st);
+  }
+  return reduce ? launch_step_t<D, S, false, true, false>(s, fin, gin, fout, gout, partials, st)
+                : launch_step_t<D, S, false, false, false>(s, fin, gin, fout, gout, partials, st);
+}
+
+template <typename Fn>
+static hipError_t by_storage(int storage, int dim, Fn&& fn) {
+  (void)dim;
+  switch (storage) {
+    case 0: return fn(float{});
+    case 1: return fn(double{});
+    case 2: return fn(__half{});
+    case 3: return fn(__hip_bfloat16{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t storage_elem_bytes(int storage) {
+  switch (storage) {
+    case 0: return 4;
+    case 1: return 8;
+    default: return 2;
+  }
+}
+
+template <int D, typename R>
+static int blocks_for(const DevState& s) {
+  using T = typename TileFor<D, R>::T;
+  return ((s.n[0] + T::TX - 1) / T::TX) * ((s.n[1] + T::TY - 1) / T::TY) * ((s.n[2] + T::TZ - 1) / T::TZ);
+}
+
+int step_blocks(const DevState& s) {
+  const bool dbl = s.storage == 1;
+  if (s.dim == 2) return dbl ? blocks_for<2, double>(s) : blocks_for<2, float>(s);
+  return dbl ? blocks_for<3, double>(s) : blocks_for<3, float>(s);
+}
+
+hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
+                       bool reduce, double* partials, hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    return s.dim == 2 ? dispatch_step<2, S>(s, fin, gin, fout, gout, reduce, partials, st)
+                      : dispatch_step<3, S>(s, fin, gin, fout, gout, reduce, partials, st);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Per-node helper kernels (set-up, I/O, statistics of a stored state)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long pitched(long long node, const int* n, int pitch) {
+  const long long x = node % n[0];
+  const long long yz = node / n[0];
+  return yz * pitch + x;
+}
+
+__global__ void fill_zero_kernel(unsigned int* p, size_t words) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t words = bytes / 4;
+  const int nb = (int)((words + 255) / 256 < 65536 ? (words + 255) / 256 : 65536);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(nb > 0 ? nb : 1), dim3(256), 0, st,
+                     static_cast<unsigned int*>(p), words);
+  return hipGetLastError();
+}
+
+template <int D>
+__host__ __device__ double flow_weight(int i) {
+  return D == 2 ? D2Q9::w(i) : D3Q19::w(i);
+}
+
+template <int D, typename S>
+__global__ void convert_in_kernel(const double* __restrict__ src, S* __restrict__ dst, int pop, int flow,
+                                  KArgs<typename Store<S>::R> a) {
+  const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
+  const double w = flow ? flow_weight<D>(pop) : 0.0;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x)
+    Store<S>::st(dst + pitched(k, a.n, a.pitch), typename Store<S>::R(src[k] - w));
+}
+
+template <int D, typename S>
+__global__ void convert_out_kernel(const S* __restrict__ src, double* __restrict__ dst, int pop, int flow,
+                                   KArgs<typename Store<S>::R> a) {
+  const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
+  const double w = flow ? flow_weight<D>(pop) : 0.0;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x)
+    dst[k] = double(Store<S>::ld(src + pitched(k, a.n, a.pitch))) + w;
+}
+
+static int node_blocks(const DevState& s) {
+  const long long nn = (long long)s.n[0] * s.n[1] * s.n[2];
+  long long nb = (nn + 255) / 256;
+  return (int)(nb < 8192 ? (nb > 0 ? nb : 1) : 8192);
+}
+
+hipError_t launch_convert_in(const DevState& s, const double* src, void* dst, int pop, int flow,
+                             hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Store<S>::R;
+    KArgs<R> a = make_args<R>(s);
+    if (s.dim == 2)
+      hipLaunchKernelGGL((convert_in_kernel<2, S>), dim3(node_blocks(s)), dim3(256), 0, st, src,
+                         static_cast<S*>(dst), pop, flow, a);
+    else
+      hipLaunchKernelGGL((convert_in_kernel<3, S>), dim3(node_blocks(s)), dim3(256), 0, st, src,
+                         static_cast<S*>(dst), pop, flow, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_convert_out(const DevState& s, const void* src, double* dst, int pop, int flow,
+                              hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Store<S>::R;
+    KArgs<R> a = make_args<R>(s);
+    if (s.dim == 2)
+      hipLaunchKernelGGL((convert_out_kernel<2, S>), dim3(node_blocks(s)), dim3(256), 0, st,
+                         static_cast<const S*>(src), dst, pop, flow, a);
+    else
+      hipLaunchKernelGGL((convert_out_kernel<3, S>), dim3(node_blocks(s)), dim3(256), 0, st,
+                         static_cast<const S*>(src), dst, pop, flow, a);
+    return hipGetLastError();
+  });
+}
+
+// Collision only (pre-collision state in, post-collision state out).
+template <int D, typename S>
+__global__ void collide_only_kernel(const S* __restrict__ fin, const S* __restrict__ gin, S* __restrict__ fout,
+                                    S* __restrict__ gout, KArgs<typename Store<S>::R> a) {
+  using R = typename Store<S>::R;
+  using LF = typename Pair<D>::F;
+  using LG = typename Pair<D>::G;
+  const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x) {
+    const long long c = pitched(k, a.n, a.pitch);
+    R d[LF::Q], g[LG::Q];
+#pragma unroll
+    for (int i = 0; i < LF::Q; ++i) d[i] = Store<S>::ld(fin + i * a.plane + c);
+#pragma unroll
+    for (int i = 0; i < LG::Q; ++i) g[i] = Store<S>::ld(gin + i * a.plane + c);
+    Macro<R> m;
+    if (a.collide) collide<D>(d, g, a.k, m);
+#pragma unroll
+    for (int i = 0; i < LF::Q; ++i) Store<S>::st(fout + i * a.plane + c, d[i]);
+#pragma unroll
+    for (int i = 0; i < LG::Q; ++i) Store<S>::st(gout + i * a.plane + c, g[i]);
+  }
+}
+
+hipError_t launch_collide_only(const DevState& s, const void* fin, const void* gin, void* fout,
+                               void* gout, hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Store<S>::R;
+    KArgs<R> a = make_args<R>(s);
+    if (s.dim == 2)
+      hipLaunchKernelGGL((collide_only_kernel<2, S>), dim3(node_blocks(s)), dim3(256), 0, st,
+                         static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
+                         static_cast<S*>(gout), a);
+    else
+      hipLaunchKernelGGL((collide_only_kernel<3, S>), dim3(node_blocks(s)), dim3(256), 0, st,
+                         static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
+                         static_cast<S*>(gout), a);
+    return hipGetLastError();
+  });
+}
+
+// Equilibrium state from (u, T) with rho = 1, collided once.
+template <int D, typename S>
+__global__ void init_eq_kernel(const double* __restrict__ ux, const double* __restrict__ uy,
+                               const double* __restrict__ uz, const double* __restrict__ Tf,
+                               S* __restrict__ fout, S* __restrict__ gout, KArgs<typename Store<S>::R> a) {
+  using R = typename Store<S>::R;
+  using LF = typename Pair<D>::F;
+  using LG = typename Pair<D>::G;
+  const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x) {
+    const R u = R(ux[k]), v = R(uy[k]), w = (D == 3 && uz) ? R(uz[k]) : R(0), T = R(Tf[k]);
+    R m[LF::Q], n[LG::Q];
+    for (int r = 0; r < LF::Q; ++r) m[r] = R(0);
+    for (int r = 0; r < LG::Q; ++r) n[r] = R(0);
+    if constexpr (D == 2) {
+      const R u2 = u * u + v * v;
+      m[1] = R(3) * u2;
+      m[2] = R(-3) * u2;
+      m[3] = u;
+      m[4] = -u;
+      m[5] = v;
+      m[6] = -v;
+      m[7] = u * u - v * v;
+      m[8] = u * v;
+      n[0] = T;
+      n[1] = u * T;
+      n[2] = v * T;
+      n[3] = a.k.aT * T;
+    } else {
+      const R u2 = u * u + v * v + w * w;
+      const R c23 = R(2.0 / 3.0);
+      const R pxx = R(2) * u * u - v * v - w * w, pww = v * v - w * w;
+      m[1] = R(19) * u2;
+      m[2] = R(-5.5) * u2;
+      m[3] = u;
+      m[4] = -c23 * u;
+      m[5] = v;
+      m[6] = -c23 * v;
+      m[7] = w;
+      m[8] = -c23 * w;
+      m[9] = pxx;
+      m[10] = R(-0.5) * pxx;
+      m[11] = pww;
+      m[12] = R(-0.5) * pww;
+      m[13] = u * v;
+      m[14] = v * w;
+      m[15] = u * w;
+      n[0] = T;
+      n[1] = u * T;
+      n[2] = v * T;
+      n[3] = w * T;
+      n[4] = a.k.aT * T;
+    }
+    R d[LF::Q], g[LG::Q];
+    from_moments<LF>(m, d);
+    from_moments<LG>(n, g);
+    Macro<R> mm;
+    if (a.collide) collide<D>(d, g, a.k, mm);
+    const long long c = pitched(k, a.n, a.pitch);
+#pragma unroll
+    for (int i = 0; i < LF::Q; ++i) Store<S>::st(fout + i * a.plane + c, d[i]);
+#pragma unroll
+    for (int i = 0; i < LG::Q; ++i) Store<S>::st(gout + i * a.plane + c, g[i]);
+  }
+}
+
+hipError_t launch_init_eq(const DevState& s, const double* ux, const double* uy, const double* uz,
+                          const double* T, void* fout, void* gout, hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Store<S>::R;
+    KArgs<R> a = make_args<R>(s);
+    if (s.dim == 2)
+      hipLaunchKernelGGL((init_eq_kernel<2, S>), dim3(node_blocks(s)), dim3(256), 0, st, ux, uy, uz, T,
+                         static_cast<S*>(fout), static_cast<S*>(gout), a);
+    else
+      hipLaunchKernelGGL((init_eq_kernel<3, S>), dim3(node_blocks(s)), dim3(256), 0, st, ux, uy, uz, T,
+                         static_cast<S*>(fout), static_cast<S*>(gout), a);
+    return hipGetLastError();
+  });
+}
+
+template <int D, typename S>
+__device__ __forceinline__ void load_node(const S* f, const S* g, long long c, long long plane,
+                                          typename Store<S>::R* d, typename Store<S>::R* gg) {
+  using LF = typename Pair<D>::F;
+  using LG = typename Pair<D>::G;
+#pragma unroll
+  for (int i = 0; i < LF::Q; ++i) d[i] = Store<S>::ld(f + i * plane + c);
+#pragma unroll
+  for (int i = 0; i < LG::Q; ++i) gg[i] = Store<S>::ld(g + i * plane + c);
+}
+
+template <int D, typename S>
+__global__ void fields_kernel(const S* __restrict__ f, const S* __restrict__ g, double* rho, double* ux,
+                              double* uy, double* uz, double* T, KArgs<typename Store<S>::R> a) {
+  using R = typename Store<S>::R;
+  const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x) {
+    R d[Pair<D>::F::Q], gg[Pair<D>::G::Q];
+    load_node<D, S>(f, g, pitched(k, a.n, a.pitch), a.plane, d, gg);
+    Macro<R> m;
+    macro_post<D>(d, gg, a.k, m);
+    if (rho) rho[k] = double(m.rho);
+    if (ux) ux[k] = double(m.u[0]);
+    if (uy) uy[k] = double(m.u[1]);
+    if (uz && D == 3) uz[k] = double(m.u[2]);
+    if (T) T[k] = double(m.T);
+  }
+}
+
+hipError_t launch_fields(const DevState& s, const void* f, const void* g, double* rho, double* ux,
+                         double* uy, double* uz, double* T, hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Store<S>::R;
+    KArgs<R> a = make_args<R>(s);
+    if (s.dim == 2)
+      hipLaunchKernelGGL((fields_kernel<2, S>), dim3(node_blocks(s)), dim3(256), 0, st,
+                         static_cast<const S*>(f), static_cast<const S*>(g), rho, ux, uy, uz, T, a);
+    else
+      hipLaunchKernelGGL((fields_kernel<3, S>), dim3(node_blocks(s)), dim3(256), 0, st,
+                         static_cast<const S*>(f), static_cast<const S*>(g), rho, ux, uy, uz, T, a);
+    return hipGetLastError();
+  });
+}
+
+// Statistics of the stored post-collision state (no time step).
+template <int D, typename S>
+__global__ void __launch_bounds__(256) reduce_state_kernel(const S* __restrict__ f, const S* __restrict__ g,
+                                                           KArgs<typename Store<S>::R> a) {
+  using R = typename Store<S>::R;
+  const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
+  RedAcc acc;
+  red_init(acc);
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x) {
+    R d[Pair<D>::F::Q], gg[Pair<D>::G::Q];
+    load_node<D, S>(f, g, pitched(k, a.n, a.pitch), a.plane, d, gg);
+    Macro<R> m;
+    macro_post<D>(d, gg, a.k, m);
+    int gi[3];
+    gi[0] = (int)(k % a.n[0]);
+    gi[1] = (int)((k / a.n[0]) % a.n[1]);
+    gi[2] = (int)(k / ((long long)a.n[0] * a.n[1]));
+    red_node(acc, a, gi, m);
+  }
+  red_block<256>(acc, a.partials + (long long)blockIdx.x * kRedSlots);
+}
+
+int reduce_state_blocks(const DevState& s) {
+  const int nb = node_blocks(s);
+  return nb < 1024 ? nb : 1024;
+}
+
+hipError_t launch_reduce_state(const DevState& s, const void* f, const void* g, double* partials,
+                               hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Store<S>::R;
+    KArgs<R> a = make_args<R>(s);
+    a.partials = partials;
+    const int nb = reduce_state_blocks(s);
+    if (s.dim == 2)
+      hipLaunchKernelGGL((reduce_state_kernel<2, S>), dim3(nb), dim3(256), 0, st,
+                         static_cast<const S*>(f), static_cast<const S*>(g), a);
+    else
+      hipLaunchKernelGGL((reduce_state_kernel<3, S>), dim3(nb), dim3(256), 0, st,
+                         static_cast<const S*>(f), static_cast<const S*>(g), a);
+    return hipGetLastError();
+  });
+}
+
+// Fixed-order sum of the per-workgroup partial records.
+__global__ void __launch_bounds__(256) finish_kernel(const double* __restrict__ partials, int nblocks,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[256];
+  for (int i = 0; i < kRedSlots; ++i) {
+    const bool mx = i >= 8 && i <= 10;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+      const double p = partials[(long long)b * kRedSlots + i];
+      v = mx ? fmax(v, p) : v + p;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w])
+                                                : sh[threadIdx.x] + sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sh[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_finish(const double* partials, int nblocks, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace islbm

@@ -1,0 +1,56 @@
+// Host-side interface of the HIP kernels (plain pointers, no torch types).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace islbm {
+
+// Everything a kernel needs about one context, in double precision; the
+// launchers convert to the arithmetic type of the storage.
+struct DevState {
+  int dim;         // 2 or 3
+  int storage;     // islbm_storage
+  int n[3];        // fluid nodes per axis (n[2] = 1 in 2-D)
+  int pitch;       // row pitch in elements (>= n[0])
+  long long plane; // elements per population plane
+  // relaxation and physics, lattice units
+  double s_e, s_eps, s_q, s_nu, s_pi, s_m, q_j, q_e, q_nu, aT;
+  double gbeta, T0, omega, Thot, Tcold;
+  double inv_uf, inv_dT;
+  int collide;     // 0 => collision is the identity
+  int uniform;     // 1 => every interpolation weight is one-hot (uniform mesh)
+  // per-axis interpolation weights: axis a holds [2][n[a]][4] of float or
+  // double (first block: lattice direction +1, second: -1); wall links are 0
+  const void* wtab[3];
+  // reduction coefficients (double): vol[a][n[a]] (V/extent), mw[a][n[a]]
+  // (V/Delta), then chot, ccold, cmv, cmd over n[0]
+  const double* red;
+  long long red_vol[3], red_mw[3], red_chot, red_ccold, red_cmv, red_cmd;
+};
+
+constexpr int kRedSlots = 12;  // 8 sums, 3 maxima, 1 non-finite count
+
+int step_blocks(const DevState& s);
+hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void* fout,
+                       void* gout, bool reduce, double* partials, hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_convert_in(const DevState& s, const double* src, void* dst, int pop, int flow,
+                             hipStream_t st);
+hipError_t launch_convert_out(const DevState& s, const void* src, double* dst, int pop, int flow,
+                              hipStream_t st);
+hipError_t launch_collide_only(const DevState& s, const void* fin, const void* gin, void* fout,
+                               void* gout, hipStream_t st);
+hipError_t launch_init_eq(const DevState& s, const double* ux, const double* uy,
+                          const double* uz, const double* T, void* fout, void* gout,
+                          hipStream_t st);
+hipError_t launch_fields(const DevState& s, const void* f, const void* g, double* rho, double* ux,
+                         double* uy, double* uz, double* T, hipStream_t st);
+int reduce_state_blocks(const DevState& s);
+hipError_t launch_reduce_state(const DevState& s, const void* f, const void* g, double* partials,
+                               hipStream_t st);
+hipError_t launch_finish(const double* partials, int nblocks, double* out, hipStream_t st);
+size_t storage_elem_bytes(int storage);
+
+}  // namespace islbm

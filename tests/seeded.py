@@ -9,15 +9,16 @@ import numpy as np
 
 
 def smooth_field(shape, rng: np.random.Generator, nmodes: int = 4) -> np.ndarray:
-    """Sum of ``nmodes`` low Fourier modes per axis with random coefficients,
-    scaled to max |value| = 1."""
-    grids = np.meshgrid(*[np.linspace(0.0, 1.0, s) for s in shape], indexing="ij")
+    """Sum of ``nmodes`` separable low Fourier modes with random
+    coefficients, scaled to max |value| = 1."""
+    axes = [np.linspace(0.0, 1.0, s) for s in shape]
     out = np.zeros(shape)
     for _ in range(nmodes):
-        term = rng.normal()
-        for g in grids:
+        term = np.array(rng.normal())
+        for d, g in enumerate(axes):
             k = rng.integers(1, 4)
-            term = term * np.cos(np.pi * k * g + rng.uniform(0, 2 * np.pi))
+            f = np.cos(np.pi * k * g + rng.uniform(0, 2 * np.pi))
+            term = term[..., None] * f if term.ndim else term * f
         out += term
     m = np.abs(out).max()
     return out / m if m > 0 else out
