@@ -179,34 +179,60 @@ __device__ __forceinline__ TileOrigin tile_origin(const int* n, const int* tiles
   return o;
 }
 
-// Stage one slot's tile (+ halo along its shifted axes) into LDS.
-template <int D, class T, int s, typename S, typename R>
-__device__ __forceinline__ void load_slot(R* lds, const S* __restrict__ fin, const S* __restrict__ gin,
-                                          const KArgs<R>& a, const TileOrigin& o) {
+// Staging of the tiles into LDS.  Every thread first issues all of its
+// global loads (a compile-time number per slot) into registers, and only then
+// writes them to LDS, so that a workgroup has its whole tile in flight at once
+// instead of one round trip per loop iteration.
+template <int D, class T>
+struct Staging {
   using SL = Slots<D, T>;
+  __host__ __device__ static constexpr int iters(int s) { return (SL::size(s) + T::NT - 1) / T::NT; }
+  __host__ __device__ static constexpr int roff(int s) {
+    int o = 0;
+    for (int k = 0; k < s; ++k) o += iters(k);
+    return o;
+  }
+  static constexpr int total = roff(SL::N);
+};
+
+template <int D, class T, int s, typename S, typename R>
+__device__ __forceinline__ void issue_slot(R* regs, const S* __restrict__ fin, const S* __restrict__ gin,
+                                           const KArgs<R>& a, const TileOrigin& o) {
+  using SL = Slots<D, T>;
+  using ST = Staging<D, T>;
   constexpr int W = SL::ext(s, 0), H = SL::ext(s, 1), V = SL::size(s);
   const S* src = (SL::isg(s) ? gin : fin) + (long long)SL::pop(s) * a.plane;
   const int ox = SL::e(s, 0) ? o.lo[0] : o.t0[0];
   const int oy = SL::e(s, 1) ? o.lo[1] : o.t0[1];
   const int oz = SL::e(s, 2) ? o.lo[2] : o.t0[2];
-  R* dst = lds + SL::off(s);
-  for (int idx = threadIdx.x; idx < V; idx += T::NT) {
+#pragma unroll
+  for (int k = 0; k < ST::iters(s); ++k) {
+    // Branch-free: positions beyond the slot or the mesh are clamped to a
+    // valid node; those LDS entries are never read by a pull.
+    int idx = threadIdx.x + k * T::NT;
+    if (V % T::NT != 0 && k + 1 == ST::iters(s)) idx = idx < V ? idx : V - 1;
     const int lz = idx / (W * H);
     const int rem = idx - lz * (W * H);
     const int ly = rem / W;
     const int lx = rem - ly * W;
-    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-    R v = R(0);
-    if (gx < a.n[0] && gy < a.n[1] && gz < a.n[2])
-      v = Store<S>::ld(src + ((long long)gz * a.n[1] + gy) * a.pitch + gx);
-    dst[idx] = v;
+    const int gx = min(ox + lx, a.n[0] - 1);
+    const int gy = min(oy + ly, a.n[1] - 1);
+    const int gz = min(oz + lz, a.n[2] - 1);
+    regs[ST::roff(s) + k] = Store<S>::ld(src + ((long long)gz * a.n[1] + gy) * a.pitch + gx);
   }
 }
 
-template <int D, class T, typename S, typename R, int... SS>
-__device__ __forceinline__ void load_all(R* lds, const S* fin, const S* gin, const KArgs<R>& a,
-                                         const TileOrigin& o, std::integer_sequence<int, SS...>) {
-  (load_slot<D, T, SS, S, R>(lds, fin, gin, a, o), ...);
+template <int D, class T, int s, typename R>
+__device__ __forceinline__ void commit_slot(R* lds, const R* regs) {
+  using SL = Slots<D, T>;
+  using ST = Staging<D, T>;
+  constexpr int V = SL::size(s);
+  R* dst = lds + SL::off(s);
+#pragma unroll
+  for (int k = 0; k < ST::iters(s); ++k) {
+    const int idx = threadIdx.x + k * T::NT;
+    if (V % T::NT == 0 || k + 1 < ST::iters(s) || idx < V) dst[idx] = regs[ST::roff(s) + k];
+  }
 }
 
 // Per-node geometry used by the pulls.
@@ -218,38 +244,25 @@ struct NodeGeo {
   int base[3];    // clamped stencil base in the shifted frame
   R wp[3][3];     // weights, direction +1, per axis
   R wm[3][3];     // weights, direction -1, per axis
+  int dep[3][2];  // uniform mesh: departure node x - e (+1, -1) in the shifted frame,
+                  // clamped into the frame for links that leave the fluid
 };
 
+// Interpolated (or, on a uniform mesh, shifted) pull of one moving
+// population.  Links that leave the fluid have all-zero weights and are
+// overwritten by wall_slot afterwards.
 template <int D, class T, int s, bool UNI, typename R>
-__device__ __forceinline__ R pull_slot(const R* lds, const NodeGeo<R>& q, const KArgs<R>& a) {
+__device__ __forceinline__ R pull_slot(const R* lds, const NodeGeo<R>& q) {
   using SL = Slots<D, T>;
   constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
   constexpr int W = SL::ext(s, 0), H = SL::ext(s, 1);
   constexpr int sy = W, sz = W * H;
   const R* L = lds + SL::off(s);
-  // wall link: the departure point lies beyond a wall on some axis
-  const bool wall = (ex == 1 && q.g[0] == 0) || (ex == -1 && q.g[0] == a.n[0] - 1) ||
-                    (ey == 1 && q.g[1] == 0) || (ey == -1 && q.g[1] == a.n[1] - 1) ||
-                    (ez == 1 && q.g[2] == 0) || (ez == -1 && q.g[2] == a.n[2] - 1);
-  if (wall) {
-    constexpr int so = SL::opps(s);
-    const R* Lo = lds + SL::off(so);
-    const int ix = ex ? q.ownh[0] : q.own[0];
-    const int iy = ey ? q.ownh[1] : q.own[1];
-    const int iz = ez ? q.ownh[2] : q.own[2];
-    const R back = Lo[ix + iy * sy + iz * sz];
-    if constexpr (SL::isg(s) && ex != 0) {
-      // anti-bounce-back on the isothermal x walls
-      const R Tw = (ex == 1) ? a.Thot : a.Tcold;
-      return -back + a.omega * Tw;
-    } else {
-      return back;  // bounce-back (no-slip, adiabatic)
-    }
-  }
   if constexpr (UNI) {
-    const int ix = ex ? q.ownh[0] - ex : q.own[0];
-    const int iy = ey ? q.ownh[1] - ey : q.own[1];
-    const int iz = ez ? q.ownh[2] - ez : q.own[2];
+    // departure node x - e (the clamped index keeps wall links in range)
+    const int ix = ex ? q.dep[0][ex > 0 ? 0 : 1] : q.own[0];
+    const int iy = ey ? q.dep[1][ey > 0 ? 0 : 1] : q.own[1];
+    const int iz = ez ? q.dep[2][ez > 0 ? 0 : 1] : q.own[2];
     return L[ix + iy * sy + iz * sz];
   } else {
     const int ix = ex ? q.base[0] : q.own[0];
@@ -283,13 +296,43 @@ __device__ __forceinline__ R pull_slot(const R* lds, const NodeGeo<R>& q, const 
   }
 }
 
+// Half-way wall rules for a link that leaves the fluid (Sec. 2.3):
+// bounce-back for f and for g on adiabatic walls, anti-bounce-back for g on
+// the isothermal x walls.
+template <int D, class T, int s, typename R>
+__device__ __forceinline__ void wall_slot(const R* lds, const NodeGeo<R>& q, const KArgs<R>& a, R& val) {
+  using SL = Slots<D, T>;
+  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
+  constexpr int W = SL::ext(s, 0), H = SL::ext(s, 1);
+  const bool wall = (ex == 1 && q.g[0] == 0) || (ex == -1 && q.g[0] == a.n[0] - 1) ||
+                    (ey == 1 && q.g[1] == 0) || (ey == -1 && q.g[1] == a.n[1] - 1) ||
+                    (ez == 1 && q.g[2] == 0) || (ez == -1 && q.g[2] == a.n[2] - 1);
+  if (!wall) return;
+  constexpr int so = SL::opps(s);
+  const R* Lo = lds + SL::off(so);
+  const int ix = ex ? q.ownh[0] : q.own[0];
+  const int iy = ey ? q.ownh[1] : q.own[1];
+  const int iz = ez ? q.ownh[2] : q.own[2];
+  const R back = Lo[ix + iy * W + iz * W * H];
+  if constexpr (SL::isg(s) && ex != 0) {
+    const R Tw = (ex == 1) ? a.Thot : a.Tcold;
+    val = -back + a.omega * Tw;
+  } else {
+    val = back;
+  }
+}
+
 template <int D, class T, bool UNI, typename R, int... SS>
 __device__ __forceinline__ void pull_all(const R* lds, const NodeGeo<R>& q, const KArgs<R>& a, R* d,
                                          R* g, std::integer_sequence<int, SS...>) {
   using SL = Slots<D, T>;
-  ((SL::isg(SS) ? (g[SL::pop(SS)] = pull_slot<D, T, SS, UNI>(lds, q, a))
-                : (d[SL::pop(SS)] = pull_slot<D, T, SS, UNI>(lds, q, a))),
+  ((SL::isg(SS) ? (g[SL::pop(SS)] = pull_slot<D, T, SS, UNI>(lds, q))
+                : (d[SL::pop(SS)] = pull_slot<D, T, SS, UNI>(lds, q))),
    ...);
+  // one branch per node: only nodes next to a wall take the wall rules
+  bool edge = q.g[0] == 0 || q.g[0] == a.n[0] - 1 || q.g[1] == 0 || q.g[1] == a.n[1] - 1;
+  if constexpr (D == 3) edge = edge || q.g[2] == 0 || q.g[2] == a.n[2] - 1;
+  if (edge) (wall_slot<D, T, SS>(lds, q, a, SL::isg(SS) ? g[SL::pop(SS)] : d[SL::pop(SS)]), ...);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,7 +414,12 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   __shared__ R lds[SL::total];
 
   const TileOrigin o = tile_origin<T>(a.n, a.tiles, a.nblocks);
-  load_all<D, T, S, R>(lds, fin, gin, a, o, std::make_integer_sequence<int, SL::N>{});
+  // 1. issue every global load of the tile (moving populations into staging
+  //    registers, rest populations and this thread's x weights directly)
+  R regs[Staging<D, T>::total];
+  [&]<int... SS>(std::integer_sequence<int, SS...>) {
+    (issue_slot<D, T, SS, S, R>(regs, fin, gin, a, o), ...);
+  }(std::make_integer_sequence<int, SL::N>{});
 
   const int lx = threadIdx.x % T::TX;
   const int r0 = threadIdx.x / T::TX;
@@ -380,7 +428,10 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   q.own[0] = lx;
   q.ownh[0] = q.g[0] - o.lo[0];
   const bool xin = q.g[0] < a.n[0];
-  // x-axis weights are shared by every node of this thread
+  if (UNI) {
+    q.dep[0][0] = q.g[0] == 0 ? q.ownh[0] : q.ownh[0] - 1;
+    q.dep[0][1] = q.g[0] == a.n[0] - 1 ? q.ownh[0] : q.ownh[0] + 1;
+  }
   if (!UNI && xin) {
     q.base[0] = clampi(q.g[0] - 1, 0, a.n[0] - 3) - o.lo[0];
 #pragma unroll
@@ -389,7 +440,6 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
       q.wm[0][c] = a.wtab[0][((long long)a.n[0] + q.g[0]) * 4 + c];
     }
   }
-  // rest populations of this thread's nodes (issued before the barrier)
   R rest_f[T::NR], rest_g[T::NR];
 #pragma unroll
   for (int k = 0; k < T::NR; ++k) {
@@ -403,6 +453,10 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
       rest_g[k] = Store<S>::ld(gin + c);
     }
   }
+  // 2. write the staged tiles to LDS
+  [&]<int... SS>(std::integer_sequence<int, SS...>) {
+    (commit_slot<D, T, SS, R>(lds, regs), ...);
+  }(std::make_integer_sequence<int, SL::N>{});
   __syncthreads();
 
   RedAcc acc;
@@ -419,7 +473,13 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
     q.own[2] = lz;
     q.ownh[1] = q.g[1] - o.lo[1];
     q.ownh[2] = q.g[2] - o.lo[2];
-    if constexpr (!UNI) {
+    if constexpr (UNI) {
+#pragma unroll
+      for (int ax = 1; ax < D; ++ax) {
+        q.dep[ax][0] = q.g[ax] == 0 ? q.ownh[ax] : q.ownh[ax] - 1;
+        q.dep[ax][1] = q.g[ax] == a.n[ax] - 1 ? q.ownh[ax] : q.ownh[ax] + 1;
+      }
+    } else {
 #pragma unroll
       for (int ax = 1; ax < D; ++ax) {
         q.base[ax] = clampi(q.g[ax] - 1, 0, a.n[ax] - 3) - o.lo[ax];
