@@ -209,7 +209,7 @@ def main() -> int:
                    "nonfinite_nodes": st["nonfinite"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "step_kernel<2,Tile<64,16,1,4>,float>",
+                     "traffic": traffic, "kernel": "step_kernel<2,Tile<64,4,1,1>,float> (cache-resident class)",
                      "bytes_per_launch": bpl, "avg_launch_us": round(per_launch * 1e6, 3)},
         "uniform": {"value": round(umlups, 1), "unit": "MLUPS",
                     "nonuniform_over_uniform": round(mlups / umlups, 4),

@@ -405,6 +405,8 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
     c->own_stream = true;
   }
   islbm_query_bytes(lattice, n, opt.storage, &c->fbytes, &c->gbytes);
+  // read + write buffers of one step against the 256 MB last-level cache
+  s.large = 2 * (c->fbytes + c->gbytes) > (size_t(192) << 20) ? 1 : 0;
   const bool given = opt.buffers[0] || opt.buffers[1] || opt.buffers[2] || opt.buffers[3];
   if (given) {
     for (int i = 0; i < 4; ++i)

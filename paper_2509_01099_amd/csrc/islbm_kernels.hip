@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "islbm_lattice.hpp"
 #include "islbm_launch.hpp"
@@ -32,29 +33,35 @@ namespace islbm {
 // ---------------------------------------------------------------------------
 template <typename S>
 struct Store;
+// st_nt: streaming store for working sets larger than the last-level cache
+// (the output of a step is not re-read until the next launch).
 template <>
 struct Store<float> {
   using R = float;
   __device__ static float ld(const float* p) { return *p; }
   __device__ static void st(float* p, float v) { *p = v; }
+  __device__ static void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<double> {
   using R = double;
   __device__ static double ld(const double* p) { return *p; }
   __device__ static void st(double* p, double v) { *p = v; }
+  __device__ static void st_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<__half> {
   using R = float;
   __device__ static float ld(const __half* p) { return __half2float(*p); }
   __device__ static void st(__half* p, float v) { *p = __float2half_rn(v); }
+  __device__ static void st_nt(__half* p, float v) { st(p, v); }
 };
 template <>
 struct Store<__hip_bfloat16> {
   using R = float;
   __device__ static float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
   __device__ static void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+  __device__ static void st_nt(__hip_bfloat16* p, float v) { st(p, v); }
 };
 
 template <typename R>
@@ -403,7 +410,7 @@ __device__ __forceinline__ void red_block(RedAcc& r, double* out) {
 // ---------------------------------------------------------------------------
 // The fused time step
 // ---------------------------------------------------------------------------
-template <int D, class T, typename S, bool UNI, bool REDUCE, bool COLLIDE>
+template <int D, class T, typename S, bool UNI, bool REDUCE, bool COLLIDE, bool NTS>
 __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, const S* __restrict__ gin,
                                                      S* __restrict__ fout, S* __restrict__ gout,
                                                      KArgs<typename Store<S>::R> a) {
@@ -508,9 +515,15 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
     }
     const long long c = ((long long)q.g[2] * a.n[1] + q.g[1]) * a.pitch + q.g[0];
 #pragma unroll
-    for (int i = 0; i < LF::Q; ++i) Store<S>::st(fout + (long long)i * a.plane + c, d[i]);
+    for (int i = 0; i < LF::Q; ++i) {
+      if constexpr (NTS) Store<S>::st_nt(fout + (long long)i * a.plane + c, d[i]);
+      else Store<S>::st(fout + (long long)i * a.plane + c, d[i]);
+    }
 #pragma unroll
-    for (int i = 0; i < LG::Q; ++i) Store<S>::st(gout + (long long)i * a.plane + c, g[i]);
+    for (int i = 0; i < LG::Q; ++i) {
+      if constexpr (NTS) Store<S>::st_nt(gout + (long long)i * a.plane + c, g[i]);
+      else Store<S>::st(gout + (long long)i * a.plane + c, g[i]);
+    }
   }
   if constexpr (REDUCE) {
     const int lb = blockIdx.x;
@@ -518,64 +531,70 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   }
 }
 
-// Tile shapes per lattice and arithmetic width.
-template <int D, typename R>
+// Tile shapes per lattice, arithmetic width and working-set class (TX x TY x
+// TZ nodes, NR nodes per thread).  "Large" means the two population buffers
+// do not fit the 256 MB last-level cache: those launches use taller tiles
+// (fewer halo re-reads) and streaming stores; cache-resident meshes use
+// short tiles (more workgroups per CU) and ordinary stores.
+template <int D, typename R, bool LARGE>
 struct TileFor;
 template <>
-struct TileFor<2, float> {
-  using T = Tile<64, 16, 1, 4>;
+struct TileFor<2, float, false> {
+  using T = Tile<64, 4, 1, 1>;
 };
 template <>
-struct TileFor<2, double> {
+struct TileFor<2, float, true> {
   using T = Tile<64, 8, 1, 2>;
 };
-template <>
-struct TileFor<3, float> {
-  using T = Tile<32, 4, 4, 2>;
+template <bool L>
+struct TileFor<2, double, L> {
+  using T = Tile<64, 8, 1, 2>;
 };
-template <>
-struct TileFor<3, double> {
+template <bool L>
+struct TileFor<3, float, L> {
+  using T = Tile<32, 4, 4, 1>;
+};
+template <bool L>
+struct TileFor<3, double, L> {
   using T = Tile<16, 4, 4, 1>;
 };
 
-template <int D, typename S>
-static void grid_of(const DevState& s, KArgs<typename Store<S>::R>& a, int& nb) {
-  using T = typename TileFor<D, typename Store<S>::R>::T;
-  a.tiles[0] = (s.n[0] + T::TX - 1) / T::TX;
-  a.tiles[1] = (s.n[1] + T::TY - 1) / T::TY;
-  a.tiles[2] = (s.n[2] + T::TZ - 1) / T::TZ;
-  nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
-  a.nblocks = nb;
+template <int D, class T>
+static int grid_of(const DevState& s, int* tiles) {
+  tiles[0] = (s.n[0] + T::TX - 1) / T::TX;
+  tiles[1] = (s.n[1] + T::TY - 1) / T::TY;
+  tiles[2] = (s.n[2] + T::TZ - 1) / T::TZ;
+  return tiles[0] * tiles[1] * tiles[2];
 }
 
-template <int D, typename S, bool UNI, bool RED, bool COL>
+template <int D, typename S, bool LARGE, bool UNI, bool RED, bool COL>
 static hipError_t launch_step_t(const DevState& s, const void* fin, const void* gin, void* fout,
                                 void* gout, double* partials, hipStream_t st) {
   using R = typename Store<S>::R;
-  using T = typename TileFor<D, R>::T;
+  using T = typename TileFor<D, R, LARGE>::T;
   KArgs<R> a = make_args<R>(s);
-  int nb = 0;
-  grid_of<D, S>(s, a, nb);
+  const int nb = grid_of<D, T>(s, a.tiles);
+  a.nblocks = nb;
   a.partials = partials;
-  hipLaunchKernelGGL((step_kernel<D, T, S, UNI, RED, COL>), dim3(nb), dim3(T::NT), 0, st,
+  hipLaunchKernelGGL((step_kernel<D, T, S, UNI, RED, COL, LARGE>), dim3(nb), dim3(T::NT), 0, st,
                      static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
                      static_cast<S*>(gout), a);
   return hipGetLastError();
 }
 
-template <int D, typename S>
+template <int D, typename S, bool LARGE>
 static hipError_t dispatch_step(const DevState& s, const void* fin, const void* gin, void* fout,
                                 void* gout, bool reduce, double* partials, hipStream_t st) {
   const bool uni = s.uniform != 0, col = s.collide != 0;
   if (col) {
     if (uni)
-      return reduce ? launch_step_t<D, S, true, true, true>(s, fin, gin, fout, gout, partials, st)
-                    : launch_step_t<D, S, true, false, true>(s, fin, gin, fout, gout, partials, st);
-    return reduce ? launch_step_t<D, S, false, true, true>(s, fin, gin, fout, gout, partials, st)
-                  : launch_step_t<D, S, false, false, true>(s, fin, gin, fout, gout, partials, st);
+      return reduce ? launch_step_t<D, S, LARGE, true, true, true>(s, fin, gin, fout, gout, partials, st)
+                    : launch_step_t<D, S, LARGE, true, false, true>(s, fin, gin, fout, gout, partials, st);
+    return reduce ? launch_step_t<D, S, LARGE, false, true, true>(s, fin, gin, fout, gout, partials, st)
+                  : launch_step_t<D, S, LARGE, false, false, true>(s, fin, gin, fout, gout, partials, st);
   }
-  return reduce ? launch_step_t<D, S, false, true, false>(s, fin, gin, fout, gout, partials, st)
-                : launch_step_t<D, S, false, false, false>(s, fin, gin, fout, gout, partials, st);
+  return reduce ? launch_step_t<D, S, LARGE, false, true, false>(s, fin, gin, fout, gout, partials, st)
+                : launch_step_t<D, S, LARGE, false, false, false>(s, fin, gin, fout, gout, partials, st);
 }
 
 template <typename Fn>
@@ -598,24 +617,36 @@ size_t storage_elem_bytes(int storage) {
   }
 }
 
-template <int D, typename R>
+template <int D, typename R, bool LARGE>
 static int blocks_for(const DevState& s) {
-  using T = typename TileFor<D, R>::T;
-  return ((s.n[0] + T::TX - 1) / T::TX) * ((s.n[1] + T::TY - 1) / T::TY) * ((s.n[2] + T::TZ - 1) / T::TZ);
+  int tiles[3];
+  return grid_of<D, typename TileFor<D, R, LARGE>::T>(s, tiles);
 }
 
 int step_blocks(const DevState& s) {
-  const bool dbl = s.storage == 1;
-  if (s.dim == 2) return dbl ? blocks_for<2, double>(s) : blocks_for<2, float>(s);
-  return dbl ? blocks_for<3, double>(s) : blocks_for<3, float>(s);
+  const bool dbl = s.storage == 1, lg = s.large != 0;
+  if (s.dim == 2) {
+    if (dbl) return blocks_for<2, double, false>(s);
+    return lg ? blocks_for<2, float, true>(s) : blocks_for<2, float, false>(s);
+  }
+  if (dbl) return blocks_for<3, double, false>(s);
+  return lg ? blocks_for<3, float, true>(s) : blocks_for<3, float, false>(s);
 }
 
 hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
                        bool reduce, double* partials, hipStream_t st) {
   return by_storage(s.storage, s.dim, [&](auto tag) {
     using S = decltype(tag);
-    return s.dim == 2 ? dispatch_step<2, S>(s, fin, gin, fout, gout, reduce, partials, st)
-                      : dispatch_step<3, S>(s, fin, gin, fout, gout, reduce, partials, st);
+    if constexpr (std::is_same_v<S, double>) {
+      return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
+                        : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
+    } else {
+      if (s.large)
+        return s.dim == 2 ? dispatch_step<2, S, true>(s, fin, gin, fout, gout, reduce, partials, st)
+                          : dispatch_step<3, S, true>(s, fin, gin, fout, gout, reduce, partials, st);
+      return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
+                        : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
+    }
   });
 }
 
