@@ -113,6 +113,167 @@ def cpu_baseline(seconds_target: float = 15.0):
                       f"{el:.1f} s"}
 
 
+def precision_study(steps: int, n: int = 384) -> dict:
+    """Storage-precision study on the 3-D workload (growth row: FP16/BF16
+    deviation storage).  The reference is the FP64 instantiation on the same
+    GPU; every variant starts at rest and runs the same number of steps."""
+    shape = (n, n, n)
+    nodes = n ** 3
+    out = {"workload": f"3-D side-heated cavity, Ra=1e7, Pr=0.71, {n}^3 tanh mesh (a=1.5), "
+                       "D3Q19+D3Q7, Ma=0.1, from rest", "steps": steps, "runs": {}}
+    ref = None
+    for st in ("fp64", "fp32", "fp16", "bf16"):
+        cav, H, uf = make_cavity("tanh", shape, storage=st, Ra=1e7, u_f=0.0)
+        t0 = time.perf_counter()
+        ms, done = 0.0, 0
+        while done < steps:
+            k = min(2000, steps - done)
+            ms += cav.time_steps(k)
+            done += k
+            _log(f"{st}: {done}/{steps} steps, {time.perf_counter() - t0:.0f}s")
+        wall = time.perf_counter() - t0
+        stats = cav.stats(allow_nonfinite=True)
+        cav.close()
+        rec = {"mlups": round(nodes * steps / wall / 1e6, 1),
+               "bytes_per_update": BYTES_PER_LU[3][st],
+               "achieved_GBs": round(BYTES_PER_LU[3][st] * nodes / (ms / 1e3 / steps) / 1e9, 1),
+               "stats": {k: stats[k] for k in ("nu_vol", "nu_hot", "nu_cold", "re_vol", "re_rms",
+                                                "umax", "vmax", "wmax", "mass")}}
+        if st == "fp64":
+            ref = rec["stats"]
+        else:
+            rec["rel_err_vs_fp64"] = {k: abs(rec["stats"][k] - ref[k]) / abs(ref[k])
+                                      for k in ("nu_vol", "nu_hot", "nu_cold", "re_vol", "re_rms",
+                                                "umax", "vmax", "wmax")}
+        out["runs"][st] = rec
+    return out
+
+
+def _log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def warmstart_data(path: str, steps: int, n_train: int = 32, n_test: int = 8,
+                   sub: int = 2) -> dict:
+    """Cold solves from rest (2-D cavity, 513^2 erf mesh a = 1.5, Pr = 0.71,
+    Ma = 0.1, FP32) at seeded log-uniform Ra in [1e6, 1e8]; 16 cavities run
+    concurrently on their own streams.  Writes the steady fields of the
+    training set (every `sub`-th node) and all Nu histories."""
+    import numpy as np
+
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    sp = W.mesh_spacing()
+    ras = W.draw_ra(n_train + n_test)
+    batches = [list(range(0, 16)), list(range(16, n_train)),
+               list(range(n_train, n_train + n_test))]
+    hist, inputs, targets, finals = {}, [], [], {}
+    t0 = time.perf_counter()
+    for b in batches:
+        cavs = [pkg.Cavity([sp, sp], float(ras[i]), PR, use_torch_buffers=False, own_stream=True)
+                for i in b]
+        uf = 0.1 / 3 ** 0.5
+
+        def log(done, h):
+            if done % 250000 == 0:
+                _log(f"batch {b[0]}..{b[-1]} step {done} t={time.perf_counter() - t0:.0f}s "
+                     f"nu_hot={[round(x[-1][1], 4) for x in h]}")
+
+        hs = W.run_concurrent(cavs, steps, 25000, log=log)
+        for i, c, h in zip(b, cavs, hs):
+            hist[i] = h
+            finals[i] = c.stats(allow_nonfinite=True)
+            if i < n_train:
+                f = W.fields_star(c, uf).reshape(513, 513, 3)[::sub, ::sub].reshape(-1, 3)
+                inputs.append(W.node_inputs(sp, float(ras[i]), sub))
+                targets.append(f.astype(np.float16))
+            c.close()
+    np.savez_compressed(path, inputs=np.concatenate(inputs), targets=np.concatenate(targets),
+                        ras=ras, n_train=n_train,
+                        hist=np.array([hist[i] for i in range(len(ras))], dtype=np.float64))
+    return {"ras": ras.tolist(), "seconds": round(time.perf_counter() - t0, 1),
+            "final_nu_hot": [finals[i]["nu_hot"] for i in range(len(ras))],
+            "final_re_rms": [finals[i]["re_rms"] for i in range(len(ras))],
+            "file": path}
+
+
+def warmstart_eval(path: str, steps: int, train_steps: int = 6000) -> dict:
+    """Trains the warm-start network on the stored steady fields, then starts
+    the held-out cavities from its prediction and compares the steps until
+    Nu_hot stays within 1e-3 of the cold-start steady value."""
+    import numpy as np
+    import torch
+
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    d = np.load(path)
+    ras, n_train, hist = d["ras"], int(d["n_train"]), d["hist"]
+    inp = torch.tensor(d["inputs"], device="cuda")
+    tgt = torch.tensor(d["targets"].astype(np.float32), device="cuda")
+    net = W.WarmStartMLP()
+    t0 = time.perf_counter()
+    losses = net.train(inp, tgt, steps=train_steps, batch=8192, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    _log(f"trained {train_steps} steps in {t_train:.1f}s, loss {losses[0][1]:.3e} -> {losses[-1][1]:.3e}")
+    # GEMM throughput of the forward pass on one mesh (dominant MFMA kernels)
+    sp = W.mesh_spacing()
+    p = torch.tensor(W.node_inputs(sp, 1e7), device="cuda")
+    net.predict(p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        net.predict(p)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t1) / 20
+    dims = net.dims
+    flops = 2 * p.shape[0] * sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+    test = list(range(n_train, len(ras)))
+    uf = 0.1 / 3 ** 0.5
+    cavs = []
+    init_err = []
+    for i in test:
+        c = pkg.Cavity([sp, sp], float(ras[i]), PR, use_torch_buffers=False, own_stream=True)
+        W.predict_init(net, c, sp, float(ras[i]), uf)
+        st = c.stats()
+        ref = hist[i][-1][1]
+        init_err.append(abs(st["nu_hot"] - ref) / ref)
+        cavs.append(c)
+
+    def log(done, h):
+        if done % 250000 == 0:
+            _log(f"warm step {done} nu_hot={[round(x[-1][1], 4) for x in h]}")
+
+    warm = W.run_concurrent(cavs, steps, 25000, log=log)
+    rows = []
+    for k, i in enumerate(test):
+        ref = hist[i][-1][1]
+        cold_h = [(r[0], r[1]) for r in hist[i]]
+        warm_h = [(r[0], r[1]) for r in warm[k]]
+        cs, ws_ = W.steps_within(cold_h, ref), W.steps_within(warm_h, ref)
+        rows.append({"Ra": float(ras[i]), "cold_steps": cs, "warm_steps": ws_,
+                     "saved": (cs - ws_) if (cs and ws_) else None,
+                     "nu_hot_steady": ref, "nu_hot_warm_end": warm[k][-1][1],
+                     "warm_end_rel_err": abs(warm[k][-1][1] - ref) / ref,
+                     "initial_rel_err": init_err[k]})
+        cavs[k].close()
+    saved = [r["saved"] for r in rows if r["saved"] is not None]
+    cold_total = sum(r["cold_steps"] or steps for r in rows)
+    warm_total = sum(r["warm_steps"] or steps for r in rows)
+    return {"study": "learned warm start, 2-D cavity 513^2 erf (a=1.5), Pr 0.71, Ma 0.1, FP32",
+            "criterion": "steps until Nu_hot stays within 1e-3 of the cold-start steady value",
+            "train": {"samples": int(inp.shape[0]), "steps": train_steps, "batch": 8192,
+                      "seconds": round(t_train, 1), "loss_first": losses[0][1],
+                      "loss_last": losses[-1][1]},
+            "inference": {"nodes": int(p.shape[0]), "ms": round(t_inf * 1e3, 3),
+                          "gemm_tflops": round(flops / t_inf / 1e12, 2)},
+            "held_out": rows, "mean_steps_saved": float(np.mean(saved)) if saved else None,
+            "cold_total_steps": cold_total, "warm_total_steps": warm_total,
+            "speedup_steps": cold_total / warm_total if warm_total else None}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +282,16 @@ def main() -> int:
     ap.add_argument("--extra", action="store_true",
                     help="also time 4096^2 2-D and 256^3 3-D meshes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--precision", type=int, default=0, metavar="STEPS",
+                    help="reduced-precision storage study instead of the headline line: "
+                         "3-D 384^3 tanh cavity, Ra 1e7, FP64/FP32/FP16/BF16, STEPS steps "
+                         "from rest, MLUPS and Nu/Re/peak-velocity errors against FP64")
+    ap.add_argument("--warmstart", choices=["data", "eval"],
+                    help="learned warm start study: 'data' runs the cold solves and writes "
+                         "--ws-file; 'eval' trains the network on it and compares warm and "
+                         "cold starts on the held-out Rayleigh numbers")
+    ap.add_argument("--ws-file", default=os.path.join(ROOT, "gpurun_out", "warm_data.npz"))
+    ap.add_argument("--ws-steps", type=int, default=2_500_000)
     ap.add_argument("--profile", action="store_true",
                     help="short run of the headline kernel only, plus a 1 GiB copy for "
                          "counter calibration (for rocprofv3)")
@@ -137,6 +308,16 @@ def main() -> int:
     pkg.load()
     n = (N_CFG, N_CFG)
     nodes = N_CFG * N_CFG
+
+    if args.warmstart == "data":
+        print(json.dumps(warmstart_data(args.ws_file, args.ws_steps)))
+        return 0
+    if args.warmstart == "eval":
+        print(json.dumps(warmstart_eval(args.ws_file, args.ws_steps)))
+        return 0
+    if args.precision:
+        print(json.dumps(precision_study(args.precision)))
+        return 0
 
     if args.profile:
         cav, H, uf = make_cavity("cosine", n)

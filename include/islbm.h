@@ -65,7 +65,8 @@ typedef enum {
 typedef enum { ISLBM_D2Q9_D2Q5 = 2, ISLBM_D3Q19_D3Q7 = 3 } islbm_lattice;
 
 /* Storage type of the populations in HBM.  Arithmetic is FP32 for FP32,
- * FP16DEV and BF16DEV (deviations f - w_i stored in half / bfloat16), and
+ * FP16DEV and BF16DEV (deviations f - w_i and g stored in half / bfloat16;
+ * FP16 scaled by 2^12, so it holds deviations up to 16 in magnitude), and
  * FP64 for FP64. */
 typedef enum { ISLBM_FP32 = 0, ISLBM_FP64 = 1, ISLBM_FP16DEV = 2, ISLBM_BF16DEV = 3 } islbm_storage;
 
@@ -100,13 +101,16 @@ typedef struct {
  * tie); re_vol = sqrt(Ra/Pr) <|u*|>_V over all velocity components, re_uv the
  * same with (u*, v*) only; mass = sum rho V / Delta^d (midpoint volumes,
  * Eq. (18)); rho_sum = plain sum of rho; umax/vmax/wmax = max |u*|, |v*|,
- * |w*|; nonfinite = number of nodes with a non-finite rho, u or T.  Averages
- * use midpoint weights normalised by the wall-to-wall extent (Sec. 2.3). */
+ * |w*|; nonfinite = number of nodes with a non-finite rho, u or T;
+ * re_rms = sqrt(Ra/Pr) sqrt(<|u*|^2>_V) (Reynolds number of the root-mean-
+ * square velocity).  Averages use midpoint weights normalised by the
+ * wall-to-wall extent (Sec. 2.3). */
 typedef struct {
   double nu_vol, nu_hot, nu_cold, nu_mid, re_vol, re_uv, mass, rho_sum;
   double umax, vmax, wmax;
   long long nonfinite;
   long long step;        /* time level t of the state the statistics describe */
+  double re_rms;
 } islbm_stats;
 
 /* Default options (all fields as described above). */

@@ -19,7 +19,7 @@ _SRC = os.path.join(_HERE, "islbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 STATS = ("nu_vol", "nu_hot", "nu_cold", "nu_mid", "re_vol", "re_uv", "mass",
-         "rho_sum", "umax", "vmax", "wmax", "nonfinite")
+         "rho_sum", "umax", "vmax", "wmax", "nonfinite", "re_rms")
 
 MESH_KINDS = {"uniform": 0, "erf": 1, "cosine": 2, "tanh": 3}
 

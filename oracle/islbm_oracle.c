@@ -712,7 +712,8 @@ static int midline(const oracle* o, int* nodes, double* cv, double* cd) {
 /* Statistics of the pre-collision state f(t), g(t).  out[]:
  *  0 <Nu>_V, 1 Nu_hot, 2 Nu_cold, 3 Nu_middle, 4 <Re>_V (|u| over all
  *  components), 5 <Re>_V with sqrt(u^2+v^2) only, 6 mass sum rho*V/Delta^d,
- *  7 sum rho, 8 max|u*|, 9 max|v*|, 10 max|w*|, 11 non-finite count. */
+ *  7 sum rho, 8 max|u*|, 9 max|v*|, 10 max|w*|, 11 non-finite count,
+ *  12 <Re> of the root-mean-square velocity, sqrt(Ra/Pr) sqrt(<|u*|^2>_V). */
 void oracle_stats(const oracle* o, double* out) {
   long nn = o->nn;
   int dim = o->dim;
@@ -724,7 +725,7 @@ void oracle_stats(const oracle* o, double* out) {
   oracle_fields(o, rho, ux, uy, uz, T);
   double dTs = (o->dT != 0.0) ? o->dT : 1.0;
   double sRaPr = sqrt(o->Ra * o->Pr), sRaoPr = sqrt(o->Ra / o->Pr);
-  double nuv = 0.0, re = 0.0, re2 = 0.0, mass = 0.0, msum = 0.0;
+  double nuv = 0.0, re = 0.0, re2 = 0.0, mass = 0.0, msum = 0.0, rms = 0.0;
   double umax = 0.0, vmax = 0.0, wmax = 0.0, bad = 0.0;
   int n0 = o->n[0], n1 = o->n[1], n2 = o->n[2];
   double dd = (dim == 2) ? o->delta * o->delta : o->delta * o->delta * o->delta;
@@ -739,6 +740,7 @@ void oracle_stats(const oracle* o, double* out) {
         nuv += W * us * Ts;
         re += W * sqrt(us * us + vs * vs + ws * ws);
         re2 += W * sqrt(us * us + vs * vs);
+        rms += W * (us * us + vs * vs + ws * ws);
         mass += rho[c] * V / dd;
         msum += rho[c];
         if (fabs(us) > umax) umax = fabs(us);
@@ -788,6 +790,7 @@ void oracle_stats(const oracle* o, double* out) {
   out[9] = vmax;
   out[10] = wmax;
   out[11] = bad;
+  out[12] = sRaoPr * sqrt(rms);
   free(rho); free(ux); free(uy); free(uz); free(T);
 }
 

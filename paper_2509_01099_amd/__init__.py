@@ -46,7 +46,7 @@ class islbm_stats(C.Structure):
                 ("nu_mid", C.c_double), ("re_vol", C.c_double), ("re_uv", C.c_double),
                 ("mass", C.c_double), ("rho_sum", C.c_double), ("umax", C.c_double),
                 ("vmax", C.c_double), ("wmax", C.c_double), ("nonfinite", C.c_longlong),
-                ("step", C.c_longlong)]
+                ("step", C.c_longlong), ("re_rms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -270,7 +270,7 @@ class Cavity:
     rest.  ``spacings`` is one array of n[a]+1 spacings per axis."""
 
     def __init__(self, spacings, Ra: float, Pr: float, storage="fp32", device="cuda:0",
-                 use_torch_buffers: bool = True, **opts):
+                 use_torch_buffers: bool = True, own_stream: bool = False, **opts):
         import torch
 
         self.dim = len(spacings)
@@ -285,8 +285,10 @@ class Cavity:
         self.device = torch.device(device)
         self._torch = torch
         with torch.cuda.device(self.device):
-            self.stream = torch.cuda.current_stream(self.device)
-            o.stream = self.stream.cuda_stream
+            # torch's current stream, or (own_stream) a stream of the library's
+            # own, so that several cavities advance concurrently
+            self.stream = None if own_stream else torch.cuda.current_stream(self.device)
+            o.stream = None if own_stream else self.stream.cuda_stream
             self._bufs = []
             if use_torch_buffers:
                 fb, gb = islbm_query_bytes(self.lattice, self.n, o.storage)
@@ -303,7 +305,10 @@ class Cavity:
             self.ctx = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone already
+            pass
 
     def step(self, n: int) -> None:
         islbm_step(self.ctx, n)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libislbm.so")
-SOURCES = ["islbm_kernels.hip", "islbm_capi.cpp"]
+SOURCES = ["islbm_kernels.hip", "islbm_capi.cpp", "islbm_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-mcode-object-version=5",
          # no packed FP32 instructions in generated code

@@ -602,6 +602,7 @@ extern "C" int islbm_nu_re(islbm_ctx* ctx, islbm_stats* out) {
   st.vmax = r[9];
   st.wmax = r[10];
   st.nonfinite = (long long)r[11];
+  st.re_rms = sRaoPr * std::sqrt(r[12]);
   st.step = ctx->t;
   *out = st;
   return st.nonfinite ? ISLBM_ENONFINITE : ISLBM_OK;

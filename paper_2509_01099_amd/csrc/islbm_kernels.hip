@@ -49,11 +49,15 @@ struct Store<double> {
   __device__ static void st(double* p, double v) { *p = v; }
   __device__ static void st_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
+// FP16 holds the deviations scaled by 2^12 (an exact power of two): deviations
+// down to ~1.5e-8 stay normal numbers; |f - w| and |g| up to 16 are
+// representable.  BF16 has the FP32 exponent range and needs no scale.
 template <>
 struct Store<__half> {
   using R = float;
-  __device__ static float ld(const __half* p) { return __half2float(*p); }
-  __device__ static void st(__half* p, float v) { *p = __float2half_rn(v); }
+  static constexpr float kScale = 4096.0f, kInv = 1.0f / 4096.0f;
+  __device__ static float ld(const __half* p) { return __half2float(*p) * kInv; }
+  __device__ static void st(__half* p, float v) { *p = __float2half_rn(v * kScale); }
   __device__ static void st_nt(__half* p, float v) { st(p, v); }
 };
 template <>
@@ -378,6 +382,7 @@ __device__ __forceinline__ void red_node(RedAcc& r, const KArgs<R>& a, const int
   r.v[10] = fmax(r.v[10], fabs(ws));
   const bool bad = !(isfinite(rho) && isfinite(us) && isfinite(vs) && isfinite(ws) && isfinite(Ts));
   r.v[11] += bad ? 1.0 : 0.0;
+  r.v[12] += W * (us * us + vs * vs + ws * ws);
 }
 
 template <int NT>

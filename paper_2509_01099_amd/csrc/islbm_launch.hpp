@@ -31,7 +31,7 @@ struct DevState {
   long long red_vol[3], red_mw[3], red_chot, red_ccold, red_cmv, red_cmd;
 };
 
-constexpr int kRedSlots = 12;  // 8 sums, 3 maxima, 1 non-finite count
+constexpr int kRedSlots = 13;  // 8 sums, 3 maxima, 1 non-finite count, 1 sum (|u*|^2)
 
 int step_blocks(const DevState& s);
 hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void* fout,

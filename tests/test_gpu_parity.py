@@ -15,7 +15,7 @@ from tests.seeded import random_populations, random_scalar_populations
 
 pytestmark = pytest.mark.gpu
 
-STAT_KEYS = ("nu_vol", "nu_hot", "nu_cold", "nu_mid", "re_vol")
+STAT_KEYS = ("nu_vol", "nu_hot", "nu_cold", "nu_mid", "re_vol", "re_rms")
 
 
 def _random_state(orc, seed):
@@ -45,7 +45,7 @@ def _compare(cav, orc, ftol, stol, what):
     st, ost = cav.stats(), orc.stats()
     errs = {}
     for k in STAT_KEYS:
-        scale = abs(ost[k]) if k == "re_vol" else _nu_scale(orc, k, ost[k])
+        scale = abs(ost[k]) if k.startswith("re_") else _nu_scale(orc, k, ost[k])
         errs[k] = abs(st[k] - ost[k]) / scale
     print(f"{what}: f {ef:.2e} g {eg:.2e} " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()),
           flush=True)
