@@ -536,6 +536,259 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3-D marching variant for uniform meshes (where the interpolation reduces to
+// a shift by one node).  A workgroup owns a TX x TY column of the mesh and
+// walks along z through a segment of ZS planes, one node per thread per
+// plane.  Populations without a z component keep one plane (plus their x/y
+// halo) in LDS; populations with a z component keep a ring of three planes.
+// While a plane is computed, the loads of the next plane are already in
+// flight in registers, so global latency overlaps the collision and z halos
+// are never re-read.  With interpolation weights and 3-tap stencils the
+// same scheme needs about 360 registers per thread, which halves occupancy
+// and is slower than the tile kernel; stretched meshes therefore use
+// step_kernel.
+// ---------------------------------------------------------------------------
+template <int TX_, int TY_, int ZS_>
+struct March {
+  static constexpr int TX = TX_, TY = TY_, ZS = ZS_, NT = TX * TY;
+  using T = Tile<TX, TY, 1, 1>;  // slot geometry: z-shifted slots hold 3 planes
+};
+
+template <class M>
+struct MStage {
+  using SL = Slots<3, typename M::T>;
+  __host__ __device__ static constexpr int plane(int s) { return SL::ext(s, 0) * SL::ext(s, 1); }
+  __host__ __device__ static constexpr int iters(int s) { return (plane(s) + M::NT - 1) / M::NT; }
+  __host__ __device__ static constexpr int roff(int s) {
+    int o = 0;
+    for (int k = 0; k < s; ++k) o += iters(k);
+    return o;
+  }
+  static constexpr int total = roff(SL::N);
+};
+
+template <class M, int s, typename S, typename R>
+__device__ __forceinline__ void issue_plane(R* regs, const S* __restrict__ fin, const S* __restrict__ gin,
+                                            const KArgs<R>& a, const TileOrigin& o, int gz) {
+  using SL = Slots<3, typename M::T>;
+  using MS = MStage<M>;
+  constexpr int W = SL::ext(s, 0), V = MS::plane(s);
+  const S* src = (SL::isg(s) ? gin : fin) + (long long)SL::pop(s) * a.plane + (long long)gz * a.n[1] * a.pitch;
+  const int ox = SL::e(s, 0) ? o.lo[0] : o.t0[0];
+  const int oy = SL::e(s, 1) ? o.lo[1] : o.t0[1];
+#pragma unroll
+  for (int k = 0; k < MS::iters(s); ++k) {
+    int idx = threadIdx.x + k * M::NT;
+    if (V % M::NT != 0 && k + 1 == MS::iters(s)) idx = idx < V ? idx : V - 1;
+    const int ly = idx / W;
+    const int lx = idx - ly * W;
+    const int gx = min(ox + lx, a.n[0] - 1);
+    const int gy = min(oy + ly, a.n[1] - 1);
+    regs[MS::roff(s) + k] = Store<S>::ld(src + (long long)gy * a.pitch + gx);
+  }
+}
+
+template <class M, int s, typename R>
+__device__ __forceinline__ void commit_plane(R* lds, const R* regs, int ring) {
+  using SL = Slots<3, typename M::T>;
+  using MS = MStage<M>;
+  constexpr int V = MS::plane(s);
+  R* dst = lds + SL::off(s) + (SL::e(s, 2) != 0 ? ring * V : 0);
+#pragma unroll
+  for (int k = 0; k < MS::iters(s); ++k) {
+    const int idx = threadIdx.x + k * M::NT;
+    if (V % M::NT == 0 || k + 1 < MS::iters(s) || idx < V) dst[idx] = regs[MS::roff(s) + k];
+  }
+}
+
+// Issue / commit the slots of one class (ZC = true: slots with a z component).
+template <class M, bool ZC, typename S, typename R, int... SS>
+__device__ __forceinline__ void issue_class(R* regs, const S* fin, const S* gin, const KArgs<R>& a,
+                                            const TileOrigin& o, int gz, std::integer_sequence<int, SS...>) {
+  using SL = Slots<3, typename M::T>;
+  ([&] {
+    if constexpr ((SL::e(SS, 2) != 0) == ZC) issue_plane<M, SS, S, R>(regs, fin, gin, a, o, gz);
+  }(), ...);
+}
+
+template <class M, bool ZC, typename R, int... SS>
+__device__ __forceinline__ void commit_class(R* lds, const R* regs, int ring, std::integer_sequence<int, SS...>) {
+  using SL = Slots<3, typename M::T>;
+  ([&] {
+    if constexpr ((SL::e(SS, 2) != 0) == ZC) commit_plane<M, SS, R>(lds, regs, ring);
+  }(), ...);
+}
+
+struct MGeo {
+  int g[3];
+  int own[2];      // own node in an unshifted x/y frame
+  int ownh[2];     // own node in a shifted x/y frame
+  int dep[2][2];   // departure node (+1, -1) in the shifted x/y frame
+  int ringown;     // ring slot of the own plane z
+  int ringdep[2];  // ring slot of plane z - 1 (+1) and z + 1 (-1)
+};
+
+template <class M, int s, typename R>
+__device__ __forceinline__ R mpull_slot(const R* lds, const MGeo& q) {
+  using SL = Slots<3, typename M::T>;
+  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
+  constexpr int W = SL::ext(s, 0), P = MStage<M>::plane(s);
+  const R* L = lds + SL::off(s);
+  const int ix = ex ? q.dep[0][ex > 0 ? 0 : 1] : q.own[0];
+  const int iy = ey ? q.dep[1][ey > 0 ? 0 : 1] : q.own[1];
+  const int iz = ez ? q.ringdep[ez > 0 ? 0 : 1] : 0;
+  return L[ix + iy * W + iz * P];
+}
+
+template <class M, int s, typename R>
+__device__ __forceinline__ void mwall_slot(const R* lds, const MGeo& q, const KArgs<R>& a, R& val) {
+  using SL = Slots<3, typename M::T>;
+  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
+  const bool wall = (ex == 1 && q.g[0] == 0) || (ex == -1 && q.g[0] == a.n[0] - 1) ||
+                    (ey == 1 && q.g[1] == 0) || (ey == -1 && q.g[1] == a.n[1] - 1) ||
+                    (ez == 1 && q.g[2] == 0) || (ez == -1 && q.g[2] == a.n[2] - 1);
+  if (!wall) return;
+  constexpr int so = SL::opps(s);
+  constexpr int W = SL::ext(so, 0), P = MStage<M>::plane(so);
+  const int ix = ex ? q.ownh[0] : q.own[0];
+  const int iy = ey ? q.ownh[1] : q.own[1];
+  const int iz = ez ? q.ringown : 0;
+  const R back = lds[SL::off(so) + ix + iy * W + iz * P];
+  if constexpr (SL::isg(s) && ex != 0) {
+    const R Tw = (ex == 1) ? a.Thot : a.Tcold;
+    val = -back + a.omega * Tw;
+  } else {
+    val = back;
+  }
+}
+
+template <class M, typename R, int... SS>
+__device__ __forceinline__ void mpull_all(const R* lds, const MGeo& q, const KArgs<R>& a, R* d, R* g,
+                                          std::integer_sequence<int, SS...>) {
+  using SL = Slots<3, typename M::T>;
+  ((SL::isg(SS) ? (g[SL::pop(SS)] = mpull_slot<M, SS>(lds, q)) : (d[SL::pop(SS)] = mpull_slot<M, SS>(lds, q))),
+   ...);
+  const bool edge = q.g[0] == 0 || q.g[0] == a.n[0] - 1 || q.g[1] == 0 || q.g[1] == a.n[1] - 1 ||
+                    q.g[2] == 0 || q.g[2] == a.n[2] - 1;
+  if (edge) (mwall_slot<M, SS>(lds, q, a, SL::isg(SS) ? g[SL::pop(SS)] : d[SL::pop(SS)]), ...);
+}
+
+template <class M, typename S, bool REDUCE, bool NTS>
+__global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fin, const S* __restrict__ gin,
+                                                        S* __restrict__ fout, S* __restrict__ gout,
+                                                        KArgs<typename Store<S>::R> a) {
+  using R = typename Store<S>::R;
+  using SL = Slots<3, typename M::T>;
+  using LF = typename SL::LF;
+  using LG = typename SL::LG;
+  using MS = MStage<M>;
+  __shared__ R lds[SL::total];
+  constexpr auto slots = std::make_integer_sequence<int, SL::N>{};
+
+  // column and z segment of this workgroup (XCD-aware numbering as in step_kernel)
+  const int b = blockIdx.x;
+  const int xcd = b & 7, loc = b >> 3;
+  const int per = a.nblocks >> 3, rem = a.nblocks & 7;
+  const int lb = xcd * per + (xcd < rem ? xcd : rem) + loc;
+  const int cols = a.tiles[0] * a.tiles[1];
+  const int col = lb % cols, seg = lb / cols;
+  TileOrigin o;
+  o.t0[0] = (col % a.tiles[0]) * M::TX;
+  o.t0[1] = (col / a.tiles[0]) * M::TY;
+  o.t0[2] = 0;
+  o.lo[0] = clampi(o.t0[0] - 1, 0, a.n[0] - 3);
+  o.lo[1] = clampi(o.t0[1] - 1, 0, a.n[1] - 3);
+  o.lo[2] = 0;
+  const int nz = a.n[2];
+  const int z0 = seg * M::ZS;
+  const int z1 = min(nz, z0 + M::ZS);
+
+  MGeo q;
+  const int lx = threadIdx.x % M::TX, ly = threadIdx.x / M::TX;
+  q.g[0] = o.t0[0] + lx;
+  q.g[1] = o.t0[1] + ly;
+  q.own[0] = lx;
+  q.own[1] = ly;
+  q.ownh[0] = q.g[0] - o.lo[0];
+  q.ownh[1] = q.g[1] - o.lo[1];
+  const bool in = q.g[0] < a.n[0] && q.g[1] < a.n[1];
+  if (in) {
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+      q.dep[ax][0] = q.g[ax] == 0 ? q.ownh[ax] : q.ownh[ax] - 1;
+      q.dep[ax][1] = q.g[ax] == a.n[ax] - 1 ? q.ownh[ax] : q.ownh[ax] + 1;
+    }
+  }
+  const long long cxy = (long long)(in ? q.g[1] : 0) * a.pitch + (in ? q.g[0] : 0);
+  const long long zstride = (long long)a.n[1] * a.pitch;
+
+  // prologue: the three stencil planes of z0 and the x/y planes of z0
+  R regs[MS::total];
+  const int zb0 = clampi(z0 - 1, 0, nz - 3);
+#pragma unroll 1
+  for (int p = 0; p < 3; ++p) {
+    issue_class<M, true, S, R>(regs, fin, gin, a, o, zb0 + p, slots);
+    commit_class<M, true, R>(lds, regs, (zb0 + p) % 3, slots);
+  }
+  issue_class<M, false, S, R>(regs, fin, gin, a, o, z0, slots);
+  R rf = Store<S>::ld(fin + (long long)z0 * zstride + cxy);
+  R rg = Store<S>::ld(gin + (long long)z0 * zstride + cxy);
+  commit_class<M, false, R>(lds, regs, 0, slots);
+  __syncthreads();
+
+  RedAcc acc;
+  if constexpr (REDUCE) red_init(acc);
+
+#pragma unroll 1
+  for (int z = z0; z < z1; ++z) {
+    const bool more = z + 1 < z1;
+    const int zb = clampi(z - 1, 0, nz - 3);
+    const int zbn = clampi(z, 0, nz - 3);
+    const bool newz = more && zbn > zb;
+    // prefetch the next plane
+    R nf = R(0), ng = R(0);
+    if (more) {
+      issue_class<M, false, S, R>(regs, fin, gin, a, o, z + 1, slots);
+      nf = Store<S>::ld(fin + (long long)(z + 1) * zstride + cxy);
+      ng = Store<S>::ld(gin + (long long)(z + 1) * zstride + cxy);
+    }
+    if (newz) issue_class<M, true, S, R>(regs, fin, gin, a, o, zbn + 2, slots);
+
+    if (in) {
+      q.g[2] = z;
+      q.ringown = z % 3;
+      q.ringdep[0] = z == 0 ? q.ringown : (z - 1) % 3;
+      q.ringdep[1] = z == nz - 1 ? q.ringown : (z + 1) % 3;
+      R d[LF::Q], g[LG::Q];
+      d[0] = rf;
+      g[0] = rg;
+      mpull_all<M>(lds, q, a, d, g, slots);
+      Macro<R> m;
+      collide<3>(d, g, a.k, m);
+      if constexpr (REDUCE) red_node(acc, a, q.g, m);
+      const long long c = (long long)z * zstride + cxy;
+#pragma unroll
+      for (int i = 0; i < LF::Q; ++i) {
+        if constexpr (NTS) Store<S>::st_nt(fout + (long long)i * a.plane + c, d[i]);
+        else Store<S>::st(fout + (long long)i * a.plane + c, d[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < LG::Q; ++i) {
+        if constexpr (NTS) Store<S>::st_nt(gout + (long long)i * a.plane + c, g[i]);
+        else Store<S>::st(gout + (long long)i * a.plane + c, g[i]);
+      }
+    }
+    __syncthreads();
+    if (more) commit_class<M, false, R>(lds, regs, 0, slots);
+    if (newz) commit_class<M, true, R>(lds, regs, (zbn + 2) % 3, slots);
+    rf = nf;
+    rg = ng;
+    __syncthreads();
+  }
+  if constexpr (REDUCE) red_block<M::NT>(acc, a.partials + (long long)blockIdx.x * kRedSlots);
+}
+
 // Tile shapes per lattice, arithmetic width and working-set class (TX x TY x
 // TZ nodes, NR nodes per thread).  "Large" means the two population buffers
 // do not fit the 256 MB last-level cache: those launches use taller tiles
@@ -602,6 +855,42 @@ static hipError_t dispatch_step(const DevState& s, const void* fin, const void* 
                 : launch_step_t<D, S, LARGE, false, false, false>(s, fin, gin, fout, gout, partials, st);
 }
 
+// Uniform 3-D meshes with collision and FP32 arithmetic (FP32 / FP16 / BF16
+// storage) use the z-marching kernel.
+using March3 = March<32, 8, 32>;
+
+static bool use_march(const DevState& s) {
+  return s.dim == 3 && s.storage != 1 && s.uniform != 0 && s.collide != 0;
+}
+
+static int march_grid(const DevState& s, int* tiles) {
+  tiles[0] = (s.n[0] + March3::TX - 1) / March3::TX;
+  tiles[1] = (s.n[1] + March3::TY - 1) / March3::TY;
+  tiles[2] = (s.n[2] + March3::ZS - 1) / March3::ZS;
+  return tiles[0] * tiles[1] * tiles[2];
+}
+
+template <typename S, bool LARGE, bool RED>
+static hipError_t launch_march_t(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
+                                 double* partials, hipStream_t st) {
+  using R = typename Store<S>::R;
+  KArgs<R> a = make_args<R>(s);
+  const int nb = march_grid(s, a.tiles);
+  a.nblocks = nb;
+  a.partials = partials;
+  hipLaunchKernelGGL((march3d_kernel<March3, S, RED, LARGE>), dim3(nb), dim3(March3::NT), 0, st,
+                     static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
+                     static_cast<S*>(gout), a);
+  return hipGetLastError();
+}
+
+template <typename S, bool LARGE>
+static hipError_t dispatch_march(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
+                                 bool reduce, double* partials, hipStream_t st) {
+  return reduce ? launch_march_t<S, LARGE, true>(s, fin, gin, fout, gout, partials, st)
+                : launch_march_t<S, LARGE, false>(s, fin, gin, fout, gout, partials, st);
+}
+
 template <typename Fn>
 static hipError_t by_storage(int storage, int dim, Fn&& fn) {
   (void)dim;
@@ -635,6 +924,10 @@ int step_blocks(const DevState& s) {
     return lg ? blocks_for<2, float, true>(s) : blocks_for<2, float, false>(s);
   }
   if (dbl) return blocks_for<3, double, false>(s);
+  if (use_march(s)) {
+    int tiles[3];
+    return march_grid(s, tiles);
+  }
   return lg ? blocks_for<3, float, true>(s) : blocks_for<3, float, false>(s);
 }
 
@@ -646,11 +939,14 @@ hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void
       return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
                         : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
     } else {
-      if (s.large)
-        return s.dim == 2 ? dispatch_step<2, S, true>(s, fin, gin, fout, gout, reduce, partials, st)
-                          : dispatch_step<3, S, true>(s, fin, gin, fout, gout, reduce, partials, st);
-      return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
-                        : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
+      if (use_march(s))
+        return s.large ? dispatch_march<S, true>(s, fin, gin, fout, gout, reduce, partials, st)
+                       : dispatch_march<S, false>(s, fin, gin, fout, gout, reduce, partials, st);
+      if (s.dim == 3)
+        return s.large ? dispatch_step<3, S, true>(s, fin, gin, fout, gout, reduce, partials, st)
+                       : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
+      return s.large ? dispatch_step<2, S, true>(s, fin, gin, fout, gout, reduce, partials, st)
+                     : dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
     }
   });
 }

@@ -38,6 +38,7 @@ def sample_nodes(shape, rng, count=4000):
     (2, "cosine", (1024, 1024), 1e8),       # the benchmark workload
     (2, "erf", (2050, 1100), 1e8),          # beyond the last-level cache: tall tiles
     (3, "tanh", (256, 256, 256), 1e7),      # the 3-D workload
+    (3, "uniform", (256, 256, 256), 1e7),   # uniform 3-D: z-marching kernel
 ])
 def test_one_step_full_size_sampled(dim, kind, n, Ra):
     oracle.set_threads(16)
