@@ -153,125 +153,126 @@ def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def warmstart_data(path: str, steps: int, n_train: int = 32, n_test: int = 8,
-                   sub: int = 2) -> dict:
-    """Cold solves from rest (2-D cavity, 513^2 erf mesh a = 1.5, Pr = 0.71,
-    Ma = 0.1, FP32) at seeded log-uniform Ra in [1e6, 1e8]; 16 cavities run
-    concurrently on their own streams.  Writes the steady fields of the
-    training set (every `sub`-th node) and all Nu histories."""
-    import numpy as np
-
-    import paper_2509_01099_amd as pkg
-    from paper_2509_01099_amd import warmstart as W
-
-    sp = W.mesh_spacing()
-    ras = W.draw_ra(n_train + n_test)
-    batches = [list(range(0, 16)), list(range(16, n_train)),
-               list(range(n_train, n_train + n_test))]
-    hist, inputs, targets, finals = {}, [], [], {}
-    t0 = time.perf_counter()
-    for b in batches:
-        cavs = [pkg.Cavity([sp, sp], float(ras[i]), PR, use_torch_buffers=False, own_stream=True)
-                for i in b]
-        uf = 0.1 / 3 ** 0.5
-
-        def log(done, h):
-            if done % 250000 == 0:
-                _log(f"batch {b[0]}..{b[-1]} step {done} t={time.perf_counter() - t0:.0f}s "
-                     f"nu_hot={[round(x[-1][1], 4) for x in h]}")
-
-        hs = W.run_concurrent(cavs, steps, 25000, log=log)
-        for i, c, h in zip(b, cavs, hs):
-            hist[i] = h
-            finals[i] = c.stats(allow_nonfinite=True)
-            if i < n_train:
-                f = W.fields_star(c, uf).reshape(513, 513, 3)[::sub, ::sub].reshape(-1, 3)
-                inputs.append(W.node_inputs(sp, float(ras[i]), sub))
-                targets.append(f.astype(np.float16))
-            c.close()
-    np.savez_compressed(path, inputs=np.concatenate(inputs), targets=np.concatenate(targets),
-                        ras=ras, n_train=n_train,
-                        hist=np.array([hist[i] for i in range(len(ras))], dtype=np.float64))
-    return {"ras": ras.tolist(), "seconds": round(time.perf_counter() - t0, 1),
-            "final_nu_hot": [finals[i]["nu_hot"] for i in range(len(ras))],
-            "final_re_rms": [finals[i]["re_rms"] for i in range(len(ras))],
-            "file": path}
-
-
-def warmstart_eval(path: str, steps: int, train_steps: int = 6000) -> dict:
-    """Trains the warm-start network on the stored steady fields, then starts
-    the held-out cavities from its prediction and compares the steps until
-    Nu_hot stays within 1e-3 of the cold-start steady value."""
+def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8,
+                    storage: str = "fp64", train_steps: int = 6000, sub: int = 2) -> dict:
+    """Learned warm start on the 2-D cavity (n^2 erf mesh a = 1.5, Pr = 0.71,
+    Ma = 0.1) at seeded log-uniform Ra in [1e6, 1e8].  Cold solves from rest
+    (16 cavities at a time, each on its own stream) give the training fields
+    (every sub-th node) and the steady Nusselt numbers; the network is
+    trained on the first n_train; the n_test held-out cavities are then
+    started from its prediction.  Criterion: steps until Nu_hot stays within
+    1e-3 of the cold-start steady value.  The same held-out cases are also
+    run with FP32 storage (cold and warm) against the same reference."""
     import numpy as np
     import torch
 
     import paper_2509_01099_amd as pkg
     from paper_2509_01099_amd import warmstart as W
 
-    d = np.load(path)
-    ras, n_train, hist = d["ras"], int(d["n_train"]), d["hist"]
-    inp = torch.tensor(d["inputs"], device="cuda")
-    tgt = torch.tensor(d["targets"].astype(np.float32), device="cuda")
-    net = W.WarmStartMLP()
+    sp = W.mesh_spacing("erf", n, 1.5)
+    ras = W.draw_ra(n_train + n_test)
+    uf = 0.1 / 3 ** 0.5
+    chunk = 20000
     t0 = time.perf_counter()
+
+    def run(ids, st, init=None, tag="cold"):
+        cavs = [pkg.Cavity([sp, sp], float(ras[i]), PR, storage=st, use_torch_buffers=False,
+                           own_stream=True) for i in ids]
+        init_nu = []
+        if init is not None:
+            for i, c in zip(ids, cavs):
+                W.predict_init(init, c, sp, float(ras[i]), uf)
+                init_nu.append(c.stats()["nu_hot"])
+
+        def log(done, h):
+            if done % 200000 == 0:
+                _log(f"{tag} {st} Ra#{ids[0]}..{ids[-1]} step {done} t={time.perf_counter() - t0:.0f}s "
+                     f"nu_hot={[round(x[-1][1], 4) for x in h]}")
+
+        t = time.perf_counter()
+        hs = W.run_concurrent(cavs, steps, chunk, log=log)
+        return cavs, hs, init_nu
+
+    hist, inputs, targets = {}, [], []
+    ids = list(range(n_train + n_test))
+    for b in range(0, len(ids), 16):
+        cavs, hs, _ = run(ids[b:b + 16], storage)
+        for i, c, h in zip(ids[b:b + 16], cavs, hs):
+            hist[i] = [(r[0], r[1]) for r in h]
+            if i < n_train:
+                f = W.fields_star(c, uf).reshape(n, n, 3)[::sub, ::sub].reshape(-1, 3)
+                inputs.append(W.node_inputs(sp, float(ras[i]), sub))
+                targets.append(f)
+            c.close()
+    ref = {i: hist[i][-1][1] for i in ids}
+    # how settled the cold references are: change over the last 10 % of the run
+    k10 = max(1, len(hist[0]) // 10)
+    settle = max(abs(hist[i][-1][1] - hist[i][-1 - k10][1]) / abs(ref[i]) for i in ids)
+
+    net = W.WarmStartMLP()
+    inp = torch.tensor(np.concatenate(inputs), device="cuda")
+    tgt = torch.tensor(np.concatenate(targets), device="cuda")
+    t1 = time.perf_counter()
     losses = net.train(inp, tgt, steps=train_steps, batch=8192, log_every=500)
     torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    t_train = time.perf_counter() - t1
     _log(f"trained {train_steps} steps in {t_train:.1f}s, loss {losses[0][1]:.3e} -> {losses[-1][1]:.3e}")
-    # GEMM throughput of the forward pass on one mesh (dominant MFMA kernels)
-    sp = W.mesh_spacing()
     p = torch.tensor(W.node_inputs(sp, 1e7), device="cuda")
     net.predict(p)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t2 = time.perf_counter()
     for _ in range(20):
         net.predict(p)
     torch.cuda.synchronize()
-    t_inf = (time.perf_counter() - t1) / 20
+    t_inf = (time.perf_counter() - t2) / 20
     dims = net.dims
     flops = 2 * p.shape[0] * sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
-    test = list(range(n_train, len(ras)))
-    uf = 0.1 / 3 ** 0.5
-    cavs = []
-    init_err = []
-    for i in test:
-        c = pkg.Cavity([sp, sp], float(ras[i]), PR, use_torch_buffers=False, own_stream=True)
-        W.predict_init(net, c, sp, float(ras[i]), uf)
-        st = c.stats()
-        ref = hist[i][-1][1]
-        init_err.append(abs(st["nu_hot"] - ref) / ref)
-        cavs.append(c)
 
-    def log(done, h):
-        if done % 250000 == 0:
-            _log(f"warm step {done} nu_hot={[round(x[-1][1], 4) for x in h]}")
-
-    warm = W.run_concurrent(cavs, steps, 25000, log=log)
+    test = ids[n_train:]
+    runs, init_nu = {}, {}
+    for st in (storage, "fp32"):
+        if st != storage:
+            cavs, hs, _ = run(test, st, tag="cold")
+            runs[(st, "cold")] = [[(r[0], r[1]) for r in h] for h in hs]
+            for c in cavs:
+                c.close()
+        else:
+            runs[(st, "cold")] = [hist[i] for i in test]
+        cavs, hs, init_nu[st] = run(test, st, init=net, tag="warm")
+        runs[(st, "warm")] = [[(r[0], r[1]) for r in h] for h in hs]
+        for c in cavs:
+            c.close()
     rows = []
     for k, i in enumerate(test):
-        ref = hist[i][-1][1]
-        cold_h = [(r[0], r[1]) for r in hist[i]]
-        warm_h = [(r[0], r[1]) for r in warm[k]]
-        cs, ws_ = W.steps_within(cold_h, ref), W.steps_within(warm_h, ref)
-        rows.append({"Ra": float(ras[i]), "cold_steps": cs, "warm_steps": ws_,
-                     "saved": (cs - ws_) if (cs and ws_) else None,
-                     "nu_hot_steady": ref, "nu_hot_warm_end": warm[k][-1][1],
-                     "warm_end_rel_err": abs(warm[k][-1][1] - ref) / ref,
-                     "initial_rel_err": init_err[k]})
-        cavs[k].close()
-    saved = [r["saved"] for r in rows if r["saved"] is not None]
-    cold_total = sum(r["cold_steps"] or steps for r in rows)
-    warm_total = sum(r["warm_steps"] or steps for r in rows)
-    return {"study": "learned warm start, 2-D cavity 513^2 erf (a=1.5), Pr 0.71, Ma 0.1, FP32",
-            "criterion": "steps until Nu_hot stays within 1e-3 of the cold-start steady value",
-            "train": {"samples": int(inp.shape[0]), "steps": train_steps, "batch": 8192,
-                      "seconds": round(t_train, 1), "loss_first": losses[0][1],
-                      "loss_last": losses[-1][1]},
-            "inference": {"nodes": int(p.shape[0]), "ms": round(t_inf * 1e3, 3),
-                          "gemm_tflops": round(flops / t_inf / 1e12, 2)},
-            "held_out": rows, "mean_steps_saved": float(np.mean(saved)) if saved else None,
-            "cold_total_steps": cold_total, "warm_total_steps": warm_total,
-            "speedup_steps": cold_total / warm_total if warm_total else None}
+        row = {"Ra": float(ras[i]), "nu_hot_steady": ref[i]}
+        for st in (storage, "fp32"):
+            for how in ("cold", "warm"):
+                h = runs[(st, how)][k]
+                row[f"{st}_{how}_steps"] = W.steps_within(h, ref[i])
+                row[f"{st}_{how}_end_rel_err"] = abs(h[-1][1] - ref[i]) / ref[i]
+            row[f"{st}_warm_initial_rel_err"] = abs(init_nu[st][k] - ref[i]) / ref[i]
+        rows.append(row)
+
+    def total(st, how):
+        return sum(r[f"{st}_{how}_steps"] or steps for r in rows)
+
+    out = {"study": f"learned warm start, 2-D cavity {n}^2 erf (a=1.5), Pr 0.71, Ma 0.1, "
+                    f"{n_train} training / {n_test} held-out Ra log-uniform in [1e6, 1e8]",
+           "criterion": "steps until Nu_hot stays within 1e-3 of the cold-start steady value "
+                        f"({storage} storage, {steps} steps)",
+           "cold_reference_settle_last10pct": settle,
+           "seconds": round(time.perf_counter() - t0, 1),
+           "train": {"samples": int(inp.shape[0]), "steps": train_steps, "batch": 8192,
+                     "seconds": round(t_train, 1), "loss_first": losses[0][1],
+                     "loss_last": losses[-1][1]},
+           "inference": {"nodes": int(p.shape[0]), "ms": round(t_inf * 1e3, 3),
+                         "gemm_tflops": round(flops / t_inf / 1e12, 2)},
+           "held_out": rows}
+    for st in (storage, "fp32"):
+        out[f"{st}_cold_total_steps"] = total(st, "cold")
+        out[f"{st}_warm_total_steps"] = total(st, "warm")
+        out[f"{st}_speedup_steps"] = total(st, "cold") / total(st, "warm")
+    return out
 
 
 def main() -> int:
@@ -286,12 +287,10 @@ def main() -> int:
                     help="reduced-precision storage study instead of the headline line: "
                          "3-D 384^3 tanh cavity, Ra 1e7, FP64/FP32/FP16/BF16, STEPS steps "
                          "from rest, MLUPS and Nu/Re/peak-velocity errors against FP64")
-    ap.add_argument("--warmstart", choices=["data", "eval"],
-                    help="learned warm start study: 'data' runs the cold solves and writes "
-                         "--ws-file; 'eval' trains the network on it and compares warm and "
-                         "cold starts on the held-out Rayleigh numbers")
-    ap.add_argument("--ws-file", default=os.path.join(ROOT, "gpurun_out", "warm_data.npz"))
-    ap.add_argument("--ws-steps", type=int, default=2_500_000)
+    ap.add_argument("--warmstart", type=int, default=0, metavar="STEPS",
+                    help="learned warm start study instead of the headline line: cold solves "
+                         "of STEPS steps give the training fields, then warm and cold starts "
+                         "are compared on held-out Rayleigh numbers")
     ap.add_argument("--profile", action="store_true",
                     help="short run of the headline kernel only, plus a 1 GiB copy for "
                          "counter calibration (for rocprofv3)")
@@ -309,11 +308,8 @@ def main() -> int:
     n = (N_CFG, N_CFG)
     nodes = N_CFG * N_CFG
 
-    if args.warmstart == "data":
-        print(json.dumps(warmstart_data(args.ws_file, args.ws_steps)))
-        return 0
-    if args.warmstart == "eval":
-        print(json.dumps(warmstart_eval(args.ws_file, args.ws_steps)))
+    if args.warmstart:
+        print(json.dumps(warmstart_study(args.warmstart)))
         return 0
     if args.precision:
         print(json.dumps(precision_study(args.precision)))

@@ -1,0 +1,58 @@
+"""The learned warm start, end to end at a small size: the solver produces
+steady fields at six Rayleigh numbers, the network (trained by the BF16
+matrix-core kernels) predicts the fields at an unseen Ra, and the solver
+started from that prediction reaches the steady Nusselt number (within 1e-3)
+in fewer steps than the cold start from rest, at the same steady value.
+
+The solver runs with FP64 storage here: with FP32 storage the slowest
+thermal modes stall once their per-step change falls below half a unit in
+the last place, so the state it settles in depends on where it started (on
+this mesh by up to ~2e-3 in Nu), and the two runs could not be compared."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _progress(tag):
+    def log(done, hist):
+        if done % 100_000 == 0:
+            print(f"{tag}: {done} steps, Nu_hot {hist[-1][-1][1]:.5f}", flush=True)
+    return log
+
+
+def test_warm_start_saves_steps():
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    sp = W.mesh_spacing("erf", 129, 1.5)
+    train_ra = [1.2e6, 2.5e6, 5e6, 1e7, 2e7, 4e7]
+    test_ra = 7e6
+    steps, chunk = 600_000, 10_000
+    uf = 0.1 / 3 ** 0.5
+    cavs = [pkg.Cavity([sp, sp], ra, 0.71, storage="fp64", use_torch_buffers=False,
+                        own_stream=True)
+            for ra in train_ra + [test_ra]]
+    hist = W.run_concurrent(cavs, steps, chunk, log=_progress("cold"))
+    inputs = np.concatenate([W.node_inputs(sp, ra) for ra in train_ra])
+    targets = np.concatenate([W.fields_star(c, uf) for c in cavs[:-1]])
+    cold = [(h[0], h[1]) for h in hist[-1]]
+    ref = cold[-1][1]
+    for c in cavs:
+        c.close()
+    net = W.WarmStartMLP()
+    losses = net.train(torch.tensor(inputs, device="cuda"), torch.tensor(targets, device="cuda"),
+                       steps=1500, batch=4096, log_every=500)
+    warm_cav = pkg.Cavity([sp, sp], test_ra, 0.71, storage="fp64", use_torch_buffers=False,
+                          own_stream=True)
+    W.predict_init(net, warm_cav, sp, test_ra, uf)
+    warm = [(h[0], h[1]) for h in W.run_concurrent([warm_cav], steps, chunk, log=_progress("warm"))[0]]
+    warm_cav.close()
+    cs, ws = W.steps_within(cold, ref), W.steps_within(warm, ref)
+    print(f"loss {losses[0][1]:.3e} -> {losses[-1][1]:.3e}; cold {cs} steps, warm {ws} steps, "
+          f"Nu_hot steady {ref:.5f}, warm end {warm[-1][1]:.5f}", flush=True)
+    assert cs is not None and ws is not None
+    assert ws < cs
+    assert abs(warm[-1][1] - ref) <= 1e-3 * ref
