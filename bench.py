@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -113,39 +114,83 @@ def cpu_baseline(seconds_target: float = 15.0):
                       f"{el:.1f} s"}
 
 
-def precision_study(steps: int, n: int = 384) -> dict:
-    """Storage-precision study on the 3-D workload (growth row: FP16/BF16
-    deviation storage).  The reference is the FP64 instantiation on the same
-    GPU; every variant starts at rest and runs the same number of steps."""
+def precision_study(steps: int, n: int = 384, steady_steps: int = 1_600_000) -> dict:
+    """Storage-precision study (growth row: FP16/BF16 deviation storage), the
+    FP64 instantiation on the same GPU being the reference.
+      throughput: MLUPS of each storage type on the 2-D benchmark workload
+        (1024^2 cosine, Ra 1e8) and the 3-D workload (n^3 tanh, Ra 1e7);
+      transient: the 3-D workload from rest for `steps` steps;
+      steady: 2-D 257^2 erf cavity at Ra 1e7 run to steady state
+        (`steady_steps`, the four storage types concurrently), with the steps
+        until Nu_hot stays within 1e-3 of the FP64 steady value."""
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    kinds = ("fp64", "fp32", "fp16", "bf16")
+    keys = ("nu_vol", "nu_hot", "nu_cold", "re_vol", "re_rms", "umax", "vmax", "wmax")
+    out = {"throughput": {}, "transient": {}, "steady": {}}
+    for st in kinds:
+        for label, kind, shape, ra, k in (("2d_cosine_1024", "cosine", (N_CFG, N_CFG), RA, 20000),
+                                          (f"3d_tanh_{n}", "tanh", (n, n, n), 1e7, 400)):
+            cav, H, uf = make_cavity(kind, shape, storage=st, Ra=ra)
+            wall, dev = time_run(cav, k, 20)
+            cav.close()
+            nodes = math.prod(shape)
+            bpl = BYTES_PER_LU[len(shape)][st]
+            out["throughput"].setdefault(label, {})[st] = {
+                "mlups": round(nodes * k / dev / 1e6, 1), "bytes_per_update": bpl,
+                "achieved_GBs": round(bpl * nodes / (dev / k) / 1e9, 1)}
+            _log(f"throughput {label} {st}: {out['throughput'][label][st]}")
+
     shape = (n, n, n)
-    nodes = n ** 3
-    out = {"workload": f"3-D side-heated cavity, Ra=1e7, Pr=0.71, {n}^3 tanh mesh (a=1.5), "
-                       "D3Q19+D3Q7, Ma=0.1, from rest", "steps": steps, "runs": {}}
+    tr = {"workload": f"3-D side-heated cavity, Ra=1e7, Pr=0.71, {n}^3 tanh mesh (a=1.5), "
+                      "D3Q19+D3Q7, Ma=0.1, from rest", "steps": steps, "runs": {}}
     ref = None
-    for st in ("fp64", "fp32", "fp16", "bf16"):
+    for st in kinds:
         cav, H, uf = make_cavity("tanh", shape, storage=st, Ra=1e7, u_f=0.0)
         t0 = time.perf_counter()
-        ms, done = 0.0, 0
+        done = 0
         while done < steps:
             k = min(2000, steps - done)
-            ms += cav.time_steps(k)
+            cav.step(k)
+            cav.sync()
             done += k
-            _log(f"{st}: {done}/{steps} steps, {time.perf_counter() - t0:.0f}s")
-        wall = time.perf_counter() - t0
+            _log(f"transient {st}: {done}/{steps} steps, {time.perf_counter() - t0:.0f}s")
         stats = cav.stats(allow_nonfinite=True)
         cav.close()
-        rec = {"mlups": round(nodes * steps / wall / 1e6, 1),
-               "bytes_per_update": BYTES_PER_LU[3][st],
-               "achieved_GBs": round(BYTES_PER_LU[3][st] * nodes / (ms / 1e3 / steps) / 1e9, 1),
-               "stats": {k: stats[k] for k in ("nu_vol", "nu_hot", "nu_cold", "re_vol", "re_rms",
-                                                "umax", "vmax", "wmax", "mass")}}
+        rec = {"stats": {k: stats[k] for k in keys + ("mass",)}}
         if st == "fp64":
             ref = rec["stats"]
         else:
-            rec["rel_err_vs_fp64"] = {k: abs(rec["stats"][k] - ref[k]) / abs(ref[k])
-                                      for k in ("nu_vol", "nu_hot", "nu_cold", "re_vol", "re_rms",
-                                                "umax", "vmax", "wmax")}
-        out["runs"][st] = rec
+            rec["rel_err_vs_fp64"] = {k: abs(rec["stats"][k] - ref[k]) / abs(ref[k]) for k in keys}
+        tr["runs"][st] = rec
+    out["transient"] = tr
+
+    sp = W.mesh_spacing("erf", 257, 1.5)
+    cavs = [pkg.Cavity([sp, sp], 1e7, PR, storage=st, use_torch_buffers=False, own_stream=True)
+            for st in kinds]
+    t0 = time.perf_counter()
+
+    def log(done, h):
+        if done % 200000 == 0:
+            _log(f"steady step {done} t={time.perf_counter() - t0:.0f}s "
+                 f"nu_hot={[round(x[-1][1], 5) for x in h]}")
+
+    hs = W.run_concurrent(cavs, steady_steps, 20000, log=log)
+    finals = [c.stats(allow_nonfinite=True) for c in cavs]
+    for c in cavs:
+        c.close()
+    nu_ref = finals[0]["nu_hot"]
+    sd = {"workload": "2-D side-heated cavity, Ra=1e7, Pr=0.71, 257^2 erf mesh (a=1.5), Ma=0.1, "
+                      "from rest", "steps": steady_steps, "runs": {}}
+    for st, h, fin in zip(kinds, hs, finals):
+        rec = {"stats": {k: fin[k] for k in keys if k != "wmax"},
+               "steps_within_1e-3_of_fp64": W.steps_within([(r[0], r[1]) for r in h], nu_ref)}
+        if st != "fp64":
+            rec["rel_err_vs_fp64"] = {k: abs(fin[k] - finals[0][k]) / abs(finals[0][k])
+                                      for k in keys if k != "wmax"}
+        sd["runs"][st] = rec
+    out["steady"] = sd
     return out
 
 
@@ -190,7 +235,7 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
                      f"nu_hot={[round(x[-1][1], 4) for x in h]}")
 
         t = time.perf_counter()
-        hs = W.run_concurrent(cavs, steps, chunk, log=log)
+        hs = W.run_concurrent(cavs, steps, chunk, log=log, steady_interval=2000)
         return cavs, hs, init_nu
 
     hist, inputs, targets = {}, [], []
@@ -198,13 +243,14 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
     for b in range(0, len(ids), 16):
         cavs, hs, _ = run(ids[b:b + 16], storage)
         for i, c, h in zip(ids[b:b + 16], cavs, hs):
-            hist[i] = [(r[0], r[1]) for r in h]
+            hist[i] = h
             if i < n_train:
                 f = W.fields_star(c, uf).reshape(n, n, 3)[::sub, ::sub].reshape(-1, 3)
                 inputs.append(W.node_inputs(sp, float(ras[i]), sub))
                 targets.append(f)
             c.close()
     ref = {i: hist[i][-1][1] for i in ids}
+    cold_steady = {i: W.steps_to_steady(hist[i]) for i in ids}
     # how settled the cold references are: change over the last 10 % of the run
     k10 = max(1, len(hist[0]) // 10)
     settle = max(abs(hist[i][-1][1] - hist[i][-1 - k10][1]) / abs(ref[i]) for i in ids)
@@ -233,13 +279,13 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
     for st in (storage, "fp32"):
         if st != storage:
             cavs, hs, _ = run(test, st, tag="cold")
-            runs[(st, "cold")] = [[(r[0], r[1]) for r in h] for h in hs]
+            runs[(st, "cold")] = hs
             for c in cavs:
                 c.close()
         else:
             runs[(st, "cold")] = [hist[i] for i in test]
         cavs, hs, init_nu[st] = run(test, st, init=net, tag="warm")
-        runs[(st, "warm")] = [[(r[0], r[1]) for r in h] for h in hs]
+        runs[(st, "warm")] = hs
         for c in cavs:
             c.close()
     rows = []
@@ -248,8 +294,10 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
         for st in (storage, "fp32"):
             for how in ("cold", "warm"):
                 h = runs[(st, how)][k]
-                row[f"{st}_{how}_steps"] = W.steps_within(h, ref[i])
+                row[f"{st}_{how}_steps"] = W.steps_within([(r[0], r[1]) for r in h], ref[i])
                 row[f"{st}_{how}_end_rel_err"] = abs(h[-1][1] - ref[i]) / ref[i]
+                row[f"{st}_{how}_steady_steps"] = W.steps_to_steady(h)
+                row[f"{st}_{how}_min_du_dT"] = [min(r[-2] for r in h), min(r[-1] for r in h)]
             row[f"{st}_warm_initial_rel_err"] = abs(init_nu[st][k] - ref[i]) / ref[i]
         rows.append(row)
 
@@ -261,6 +309,8 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
            "criterion": "steps until Nu_hot stays within 1e-3 of the cold-start steady value "
                         f"({storage} storage, {steps} steps)",
            "cold_reference_settle_last10pct": settle,
+           "steady_criterion": "Sec. 3: relative change of u and T over 2000 steps below 1e-9",
+           "cold_steps_to_steady_criterion_all": [cold_steady[i] for i in ids],
            "seconds": round(time.perf_counter() - t0, 1),
            "train": {"samples": int(inp.shape[0]), "steps": train_steps, "batch": 8192,
                      "seconds": round(t_train, 1), "loss_first": losses[0][1],

@@ -158,6 +158,20 @@ int islbm_fields_device(islbm_ctx* ctx, double* rho, double* ux, double* uy, dou
  * ISLBM_ENONFINITE (with *out filled) when a node is non-finite. */
 int islbm_nu_re(islbm_ctx* ctx, islbm_stats* out);
 
+/* Steady-state measure of Sec. 3 (the convergence criterion there, with the
+ * caller choosing the interval, 2000 steps in the paper): with u, T the
+ * current fields (as islbm_fields) and u', T' those of the previous call,
+ *   *du = sum_nodes |u - u'|_2 / sum_nodes |u'|_2,
+ *   *dT = sum_nodes |T - T'|   / sum_nodes |T'|,
+ * summed in FP64 in a fixed order; a zero denominator gives 0 (no change) or
+ * +inf.  The current fields then become the snapshot (4 n_x n_y n_z doubles
+ * of device memory, allocated on the first call and kept by the context).
+ * The first call, and the first after islbm_set_populations,
+ * islbm_load_state or islbm_init_fields[_device], only takes the snapshot
+ * and returns +inf for both.  *steps (may be NULL) receives the time steps
+ * between the two field sets.  Synchronises the stream. */
+int islbm_steady_change(islbm_ctx* ctx, double* du, double* dT, long long* steps);
+
 /* Copies the post-collision state to host arrays f [q_f][nodes] and
  * g [q_g][nodes] (either may be NULL).  Synchronises the stream. */
 int islbm_get_populations(islbm_ctx* ctx, double* f, double* g);

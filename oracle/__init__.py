@@ -140,6 +140,26 @@ def wall_derivative(top: int, q: float, phiw: float, phi1: float, phi2: float) -
     return _load().oracle_wall_derivative(top, q, phiw, phi1, phi2)
 
 
+def steady_change(before: dict, after: dict) -> tuple:
+    """Steady-state measure of Sec. 3 (its convergence criterion, applied in
+    the paper to fields 2000 steps apart): the summed 2-norm of the velocity
+    change over the summed 2-norm of the earlier velocity, and the summed
+    absolute temperature change over the summed absolute earlier
+    temperature.  ``before`` / ``after`` are field dicts as from
+    ``Oracle.fields`` (uz may be absent or zero in 2-D)."""
+    def vel(f):
+        uz = f.get("uz")
+        return f["ux"], f["uy"], (np.zeros_like(f["ux"]) if uz is None else uz)
+
+    bx, by, bz = vel(before)
+    ax, ay, az = vel(after)
+    num_u = np.sum(np.sqrt((ax - bx) ** 2 + (ay - by) ** 2 + (az - bz) ** 2))
+    den_u = np.sum(np.sqrt(bx ** 2 + by ** 2 + bz ** 2))
+    num_T = np.sum(np.abs(after["T"] - before["T"]))
+    den_T = np.sum(np.abs(before["T"]))
+    return float(num_u / den_u), float(num_T / den_T)
+
+
 def set_threads(n: int) -> None:
     _load().oracle_set_threads(n)
 

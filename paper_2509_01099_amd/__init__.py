@@ -28,7 +28,8 @@ EXPORTS = ("islbm_default_options", "islbm_query_bytes", "islbm_mesh_spacing", "
            "islbm_get_populations", "islbm_set_populations", "islbm_init_fields",
            "islbm_init_fields_device", "islbm_info", "islbm_time", "islbm_set_time",
            "islbm_sync", "islbm_destroy", "islbm_strerror", "islbm_last_error",
-           "islbm_time_steps", "islbm_state_bytes", "islbm_save_state", "islbm_load_state")
+           "islbm_time_steps", "islbm_state_bytes", "islbm_save_state", "islbm_load_state",
+           "islbm_steady_change")
 
 
 class islbm_options(C.Structure):
@@ -104,6 +105,7 @@ def load() -> C.CDLL:
     lib.islbm_state_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
     lib.islbm_save_state.argtypes = [P, C.c_void_p, C.c_size_t]
     lib.islbm_load_state.argtypes = [P, C.c_void_p, C.c_size_t]
+    lib.islbm_steady_change.argtypes = [P, _D, _D, C.POINTER(C.c_longlong)]
     special = {"islbm_default_options", "islbm_destroy", "islbm_strerror", "islbm_last_error",
                "islbm_time"}
     for name in EXPORTS:
@@ -183,6 +185,13 @@ def islbm_nu_re(ctx, allow_nonfinite: bool = False) -> dict:
     if not (allow_nonfinite and rc == ISLBM_ENONFINITE):
         _check(rc, ctx)
     return st.as_dict()
+
+
+def islbm_steady_change(ctx) -> tuple:
+    """(du, dT, steps) since the previous call; (inf, inf, 0) on the first."""
+    du, dT, k = C.c_double(), C.c_double(), C.c_longlong()
+    _check(load().islbm_steady_change(ctx, C.byref(du), C.byref(dT), C.byref(k)), ctx)
+    return du.value, dT.value, k.value
 
 
 def islbm_fields(ctx, shape) -> dict:
@@ -321,6 +330,9 @@ class Cavity:
 
     def fields(self) -> dict:
         return islbm_fields(self.ctx, self.shape)
+
+    def steady_change(self) -> tuple:
+        return islbm_steady_change(self.ctx)
 
     def populations(self):
         return islbm_get_populations(self.ctx, self.qf, self.qg, self.shape)

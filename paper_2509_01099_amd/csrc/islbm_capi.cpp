@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -38,6 +39,10 @@ struct islbm_ctx {
   double* hres = nullptr;
   double* staging = nullptr;
   double* fields_dev = nullptr;
+  double* snap = nullptr;        // steady-change snapshot: ux, uy, uz, T (nn doubles each)
+  double* snap_part = nullptr;   // its per-workgroup partial sums (4 doubles per workgroup)
+  bool snap_valid = false;
+  long long snap_t = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -165,6 +170,8 @@ static void release(islbm_ctx* c) {
   if (c->hres) hipHostFree(c->hres);
   if (c->staging) hipFree(c->staging);
   if (c->fields_dev) hipFree(c->fields_dev);
+  if (c->snap) hipFree(c->snap);
+  if (c->snap_part) hipFree(c->snap_part);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -608,6 +615,32 @@ extern "C" int islbm_nu_re(islbm_ctx* ctx, islbm_stats* out) {
   return st.nonfinite ? ISLBM_ENONFINITE : ISLBM_OK;
 }
 
+extern "C" int islbm_steady_change(islbm_ctx* ctx, double* du, double* dT, long long* steps) {
+  if (!ctx || !du || !dT) return ISLBM_EINVAL;
+  const int nb = islbm::reduce_state_blocks(ctx->s);
+  if (!ctx->snap) HIPCHECK(ctx, hipMalloc(&ctx->snap, (size_t)ctx->nn * 4 * sizeof(double)));
+  if (!ctx->snap_part) HIPCHECK(ctx, hipMalloc(&ctx->snap_part, (size_t)nb * 4 * sizeof(double)));
+  const bool first = !ctx->snap_valid;
+  hipError_t e = islbm::launch_steady_change(ctx->s, fbuf(ctx, ctx->cur), gbuf(ctx, ctx->cur), ctx->snap,
+                                             first ? 1 : 0, ctx->snap_part, ctx->stream);
+  if (e != hipSuccess) return hipfail(ctx, e, "steady-change kernel");
+  std::vector<double> h((size_t)nb * 4);
+  HIPCHECK(ctx, hipMemcpyAsync(h.data(), ctx->snap_part, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < nb; ++b)
+    for (int i = 0; i < 4; ++i) sum[i] += h[(size_t)b * 4 + i];
+  const double inf = std::numeric_limits<double>::infinity();
+  auto ratio = [&](double num, double den) { return den > 0.0 ? num / den : (num > 0.0 ? inf : 0.0); };
+  *du = first ? inf : ratio(sum[0], sum[1]);
+  *dT = first ? inf : ratio(sum[2], sum[3]);
+  if (steps) *steps = first ? 0 : ctx->t - ctx->snap_t;
+  ctx->snap_valid = true;
+  ctx->snap_t = ctx->t;
+  return ISLBM_OK;
+}
+
 static int ensure_staging(islbm_ctx* c) {
   if (c->staging) return ISLBM_OK;
   hipError_t e = hipMalloc(&c->staging, (size_t)c->nn * sizeof(double));
@@ -663,6 +696,7 @@ extern "C" int islbm_set_populations(islbm_ctx* ctx, const double* f, const doub
     if (e != hipSuccess) return hipfail(ctx, e, "collide kernel");
   }
   ctx->partials_valid = false;
+  ctx->snap_valid = false;
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   return ISLBM_OK;
 }
@@ -674,6 +708,7 @@ extern "C" int islbm_init_fields_device(islbm_ctx* ctx, const double* ux, const 
                                        ctx->stream);
   if (e != hipSuccess) return hipfail(ctx, e, "init kernel");
   ctx->partials_valid = false;
+  ctx->snap_valid = false;
   return ISLBM_OK;
 }
 
@@ -745,5 +780,6 @@ extern "C" int islbm_load_state(islbm_ctx* ctx, const void* host, size_t bytes) 
                                ctx->stream));
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->partials_valid = false;
+  ctx->snap_valid = false;
   return ISLBM_OK;
 }

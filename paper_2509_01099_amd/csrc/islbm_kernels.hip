@@ -1254,6 +1254,73 @@ hipError_t launch_reduce_state(const DevState& s, const void* f, const void* g, 
   });
 }
 
+// Change of the velocity and temperature fields against a snapshot u', T'
+// taken earlier (the steady-state measure of Sec. 3): per workgroup, sums of
+// |u - u'|_2, |u'|_2, |T - T'| and |T'| in FP64; the snapshot is then
+// overwritten with the current fields (snap holds ux, uy, uz, T planes of nn
+// doubles each).
+template <int D, typename S>
+__global__ void __launch_bounds__(256) steady_change_kernel(const S* __restrict__ f, const S* __restrict__ g,
+                                                            double* __restrict__ snap, int first,
+                                                            double* __restrict__ partials,
+                                                            KArgs<typename Store<S>::R> a) {
+  using R = typename Store<S>::R;
+  const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x) {
+    R d[Pair<D>::F::Q], gg[Pair<D>::G::Q];
+    load_node<D, S>(f, g, pitched(k, a.n, a.pitch), a.plane, d, gg);
+    Macro<R> m;
+    macro_post<D>(d, gg, a.k, m);
+    const double u0 = double(m.u[0]), u1 = double(m.u[1]), u2 = D == 3 ? double(m.u[2]) : 0.0;
+    const double T = double(m.T);
+    if (!first) {
+      const double p0 = snap[k], p1 = snap[nn + k], p2 = snap[2 * nn + k], pT = snap[3 * nn + k];
+      const double e0 = u0 - p0, e1 = u1 - p1, e2 = u2 - p2;
+      acc[0] += sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+      acc[1] += sqrt(p0 * p0 + p1 * p1 + p2 * p2);
+      acc[2] += fabs(T - pT);
+      acc[3] += fabs(pT);
+    }
+    snap[k] = u0;
+    snap[nn + k] = u1;
+    snap[2 * nn + k] = u2;
+    snap[3 * nn + k] = T;
+  }
+  __shared__ double sh[4][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double v = acc[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) sh[wid][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int i = threadIdx.x;
+    partials[(long long)blockIdx.x * 4 + i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+  }
+}
+
+hipError_t launch_steady_change(const DevState& s, const void* f, const void* g, double* snap, int first,
+                                double* partials, hipStream_t st) {
+  return by_storage(s.storage, s.dim, [&](auto tag) {
+    using S = decltype(tag);
+    using R = typename Store<S>::R;
+    KArgs<R> a = make_args<R>(s);
+    const int nb = reduce_state_blocks(s);
+    if (s.dim == 2)
+      hipLaunchKernelGGL((steady_change_kernel<2, S>), dim3(nb), dim3(256), 0, st, static_cast<const S*>(f),
+                         static_cast<const S*>(g), snap, first, partials, a);
+    else
+      hipLaunchKernelGGL((steady_change_kernel<3, S>), dim3(nb), dim3(256), 0, st, static_cast<const S*>(f),
+                         static_cast<const S*>(g), snap, first, partials, a);
+    return hipGetLastError();
+  });
+}
+
 // Fixed-order sum of the per-workgroup partial records.
 __global__ void __launch_bounds__(256) finish_kernel(const double* __restrict__ partials, int nblocks,
                                                      double* __restrict__ out) {

@@ -52,6 +52,8 @@ int reduce_state_blocks(const DevState& s);
 hipError_t launch_reduce_state(const DevState& s, const void* f, const void* g, double* partials,
                                hipStream_t st);
 hipError_t launch_finish(const double* partials, int nblocks, double* out, hipStream_t st);
+hipError_t launch_steady_change(const DevState& s, const void* f, const void* g, double* snap, int first,
+                                double* partials, hipStream_t st);
 size_t storage_elem_bytes(int storage);
 
 }  // namespace islbm

@@ -297,22 +297,43 @@ def steps_within(history, ref: float, tol: float = 1e-3) -> int | None:
     return ok_from
 
 
-def run_concurrent(cavs, steps: int, chunk: int, keys=("nu_hot", "nu_vol", "re_rms"), log=None):
+def run_concurrent(cavs, steps: int, chunk: int, keys=("nu_hot", "nu_vol", "re_rms"), log=None,
+                   steady_interval: int = 0):
     """Advances every cavity by `steps` in chunks (each cavity on its own
-    stream, so the launches overlap); records statistics after each chunk."""
+    stream, so the launches overlap); records statistics after each chunk.
+    With steady_interval > 0 each record also carries the Sec. 3 steady-state
+    measure (du, dT) over the last steady_interval steps of the chunk."""
     hist = [[] for _ in cavs]
     done = 0
     while done < steps:
         n = min(chunk, steps - done)
+        lead = n - steady_interval if 0 < steady_interval < n else n
         for c in cavs:
-            c.step(n)
+            c.step(lead)
+        if lead < n:
+            for c in cavs:
+                c.steady_change()
+            for c in cavs:
+                c.step(n - lead)
         done += n
         for h, c in zip(hist, cavs):
             st = c.stats(allow_nonfinite=True)
-            h.append((done, *[st[k] for k in keys]))
+            rec = (done, *[st[k] for k in keys])
+            if lead < n:
+                rec = rec + c.steady_change()[:2]
+            h.append(rec)
         if log:
             log(done, hist)
     return hist
+
+
+def steps_to_steady(history, tol: float = 1e-9):
+    """First recorded step at which both steady-state measures (the last two
+    entries of a record) are below tol (Sec. 3 uses 1e-9); None if never."""
+    for rec in history:
+        if rec[-2] < tol and rec[-1] < tol:
+            return rec[0]
+    return None
 
 
 def fields_star(cav, uf: float) -> np.ndarray:

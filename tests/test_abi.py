@@ -103,4 +103,5 @@ def test_strerror_and_null_handling():
     lib.islbm_destroy(None)                  # no-op
     assert lib.islbm_step(None, 1) == pkg.ISLBM_EINVAL
     assert lib.islbm_nu_re(None, None) == pkg.ISLBM_EINVAL
+    assert lib.islbm_steady_change(None, None, None, None) == pkg.ISLBM_EINVAL
     assert lib.islbm_time(None) == -1

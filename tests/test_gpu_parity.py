@@ -192,6 +192,33 @@ def test_stream_only_reproduces_quadratics(dim, kind):
     cav.close()
 
 
+@pytest.mark.parametrize("dim,storage,tol", [(2, "fp32", 1e-5), (2, "fp64", 1e-11),
+                                             (3, "fp32", 1e-5)])
+def test_steady_change_matches_oracle(dim, storage, tol):
+    """Sec. 3 steady-state measure between two times 50 steps apart from a
+    seeded random state, against the oracle's fields at the same times."""
+    oracle.set_threads(16)
+    meshes = [("erf", 46, 1.5), ("erf", 30, 1.5), ("erf", 12, 1.5)][:dim]
+    cav, orc = make_pair(meshes, 1e6, 0.71, storage=storage)
+    f, g = _random_state(orc, 9)
+    cav.set_populations(f, g, post_collision=False)
+    orc.set_state(f, g)
+    first = cav.steady_change()
+    assert first[0] == np.inf and first[1] == np.inf and first[2] == 0
+    before = orc.fields()
+    cav.step(50)
+    orc.run(50)
+    du, dT, k = cav.steady_change()
+    odu, odT = oracle.steady_change(before, orc.fields())
+    print(f"{dim}d {storage}: du {du:.6e} ({odu:.6e}) dT {dT:.6e} ({odT:.6e})", flush=True)
+    assert k == 50
+    assert abs(du - odu) <= tol * odu and abs(dT - odT) <= tol * odT
+    # a replaced state restarts the measure
+    cav.set_populations(f, g, post_collision=False)
+    assert cav.steady_change()[0] == np.inf
+    cav.close()
+
+
 def test_checkpoint_restore_is_bitwise():
     """run(2n) equals run(n) -> save -> new context -> restore -> run(n)."""
     meshes = [("tanh", 90, 1.5), ("tanh", 50, 1.5)]

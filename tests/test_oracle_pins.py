@@ -475,3 +475,30 @@ def test_conduction_limit(kind):
     wall0, wall1 = 0.5 * (x[0] + x[1]), 0.5 * (x[-2] + x[-1])
     lin = 0.5 - (x[1:-1] - wall0) / (wall1 - wall0)
     assert np.abs(T - lin[None, :]).max() < 1e-9
+
+
+def test_steady_change_hand_example():
+    """Sec. 3 steady-state measure on a two-node field worked by hand:
+    velocity changes of length 5 and 1 over earlier speeds 5 and 0; one
+    temperature changes by 1 against earlier |T| 2 + 2."""
+    before = {"ux": np.array([3.0, 0.0]), "uy": np.array([4.0, 0.0]), "T": np.array([2.0, -2.0])}
+    after = {"ux": np.array([0.0, 0.0]), "uy": np.array([0.0, 1.0]), "T": np.array([1.0, -2.0])}
+    du, dT = oracle.steady_change(before, after)
+    assert du == pytest.approx(6.0 / 5.0, rel=1e-15)
+    assert dT == pytest.approx(0.25, rel=1e-15)
+
+
+def test_steady_change_scaling_and_fixed_point():
+    """A uniform rescaling by (1 + e) changes both measures by exactly e; an
+    unchanged field gives zero; the 3-D component enters the 2-norm."""
+    rng = np.random.default_rng(3)
+    f = {k: rng.normal(size=(5, 6, 7)) for k in ("ux", "uy", "uz", "T")}
+    e = 1e-3
+    g = {k: v * (1 + e) for k, v in f.items()}
+    du, dT = oracle.steady_change(f, g)
+    assert du == pytest.approx(e, rel=1e-9) and dT == pytest.approx(e, rel=1e-9)
+    assert oracle.steady_change(f, f) == (0.0, 0.0)
+    h = dict(f, uz=f["uz"] + 1.0)
+    du3, _ = oracle.steady_change(f, h)
+    assert du3 == pytest.approx(f["uz"].size / np.sum(np.sqrt(f["ux"] ** 2 + f["uy"] ** 2
+                                                              + f["uz"] ** 2)), rel=1e-12)
