@@ -194,6 +194,92 @@ def precision_study(steps: int, n: int = 384, steady_steps: int = 1_600_000) -> 
     return out
 
 
+def _wall_coords(sp):
+    """Fluid-node coordinates measured from the first wall, in units of the
+    wall-to-wall extent (meshes of different N then share one frame)."""
+    import numpy as np
+
+    X = np.concatenate([[0.0], np.cumsum(sp)])
+    w0 = 0.5 * (X[0] + X[1])
+    return (X[1:-1] - w0) / (0.5 * (X[-1] + X[-2]) - w0)
+
+
+def converge(cav, max_steps: int, tol: float = 1e-9, interval: int = 2000,
+             check: int = 50000, tag: str = ""):
+    """Runs until the Sec. 3 steady-state measure over `interval` steps is
+    below `tol` for both u and T (checked every `check` steps)."""
+    done, t0 = 0, time.perf_counter()
+    du = dT = float("inf")
+    while done < max_steps:
+        cav.step(check - interval)
+        cav.steady_change()
+        cav.step(interval)
+        du, dT, _ = cav.steady_change()
+        done += check
+        if done % 500000 == 0:
+            _log(f"{tag} step {done} du {du:.2e} dT {dT:.2e} t={time.perf_counter() - t0:.0f}s")
+        if du < tol and dT < tol:
+            break
+    return done, du, dT, time.perf_counter() - t0
+
+
+def convergence_study(Ra: float = 1e6, sizes=(257, 513, 1025), max_steps: int = 4_000_000,
+                      storage: str = "fp64") -> dict:
+    """Grid convergence of the steady 2-D cavity on erf meshes (a = 1.5)
+    refined by 2: each mesh starts from the previous mesh's steady fields
+    (interpolated) and runs to the Sec. 3 steady criterion; the observed
+    order p and the extrapolated value follow the Richardson formulas of
+    Sec. 3, and GCI_fine uses a safety factor of 1.25."""
+    import numpy as np
+    from scipy.interpolate import RegularGridInterpolator
+
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    keys = ("nu_vol", "nu_hot", "nu_mid", "re_rms")
+    uf = 0.1 / 3 ** 0.5
+    vals, runs, prev = {}, [], None
+    for n in sizes:
+        sp = W.mesh_spacing("erf", n, 1.5)
+        cav = pkg.Cavity([sp, sp], Ra, PR, storage=storage, use_torch_buffers=False)
+        c = _wall_coords(sp)
+        if prev is not None:
+            pc, pf = prev
+            yy, xx = np.meshgrid(c, c, indexing="ij")
+            pts = np.column_stack([yy.ravel(), xx.ravel()])
+            init = {}
+            for k in ("ux", "uy", "T"):
+                ip = RegularGridInterpolator((pc, pc), pf[k], method="linear", bounds_error=False,
+                                             fill_value=None)
+                init[k] = ip(pts).reshape(n, n)
+            # velocities scale with u_f in every mesh's own lattice units
+            cav.init_fields(init["ux"], init["uy"], None, init["T"])
+        steps, du, dT, secs = converge(cav, max_steps, tag=f"{n}^2")
+        st = cav.stats()
+        f = cav.fields()
+        prev = (c, {k: f[k] for k in ("ux", "uy", "T")})
+        vals[n] = {k: st[k] for k in keys}
+        runs.append({"n": n, "steps": steps, "du": du, "dT": dT, "seconds": round(secs, 1),
+                     "mlups": round(n * n * steps / secs / 1e6, 1), **vals[n]})
+        _log(f"{n}^2: {runs[-1]}")
+        cav.close()
+    out = {"workload": f"2-D cavity Ra={Ra:g} Pr=0.71, erf meshes a=1.5, {storage}, "
+                       "each refined mesh initialised from the previous steady fields",
+           "runs": runs}
+    if len(sizes) == 3:
+        a, b, c3 = sizes
+        r = 2.0
+        rich = {}
+        for k in keys:
+            fc, fm, ff = vals[a][k], vals[b][k], vals[c3][k]
+            p = math.log(abs((fc - fm) / (fm - ff))) / math.log(r)
+            finf = (r ** p * ff - fm) / (r ** p - 1)
+            gci = 1.25 * abs((ff - fm) / ff) / (r ** p - 1) * 100
+            rich[k] = {"p": p, "extrapolated": finf, "gci_fine_pct": gci}
+        out["richardson"] = rich
+    return out
+
+
 def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -341,6 +427,13 @@ def main() -> int:
                     help="learned warm start study instead of the headline line: cold solves "
                          "of STEPS steps give the training fields, then warm and cold starts "
                          "are compared on held-out Rayleigh numbers")
+    ap.add_argument("--convergence", type=float, default=0.0, metavar="RA",
+                    help="grid-convergence study instead of the headline line: 2-D cavity at "
+                         "this Ra on erf meshes 257/513/1025 (1e6) or 513/1025/2049, FP64, "
+                         "run to the steady criterion; observed order and extrapolation")
+    ap.add_argument("--profile-mesh", choices=["2d", "3d", "3d-uniform"], default="2d",
+                    help="workload of --profile: the 2-D benchmark mesh, the 3-D 256^3 tanh "
+                         "mesh (Ra 1e7) or the 3-D 256^3 uniform mesh")
     ap.add_argument("--profile", action="store_true",
                     help="short run of the headline kernel only, plus a 1 GiB copy for "
                          "counter calibration (for rocprofv3)")
@@ -358,6 +451,10 @@ def main() -> int:
     n = (N_CFG, N_CFG)
     nodes = N_CFG * N_CFG
 
+    if args.convergence:
+        sizes = (257, 513, 1025) if args.convergence < 5e6 else (513, 1025, 2049)
+        print(json.dumps(convergence_study(args.convergence, sizes)))
+        return 0
     if args.warmstart:
         print(json.dumps(warmstart_study(args.warmstart)))
         return 0
@@ -366,7 +463,10 @@ def main() -> int:
         return 0
 
     if args.profile:
-        cav, H, uf = make_cavity("cosine", n)
+        shape = {"2d": n, "3d": (256, 256, 256), "3d-uniform": (256, 256, 256)}[args.profile_mesh]
+        kind = "uniform" if args.profile_mesh == "3d-uniform" else ("tanh" if len(shape) == 3 else "cosine")
+        cav, H, uf = make_cavity(kind, shape, Ra=RA if len(shape) == 2 else 1e7)
+        nodes = math.prod(shape)
         wall, dev = time_run(cav, args.steps, args.warmup)
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -17,11 +17,12 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_table2_ra1e6_257():
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_table2_ra1e6_257(storage):
     ref = json.load(open(os.path.join(HERE, "golden", "table2_ra1e6.json")))["rows"]["257"]
     sp = pkg.islbm_mesh_spacing("erf", 257, 1.5)
     sp = sp / sp[0]
-    cav = pkg.Cavity([sp, sp], 1e6, 0.71)      # Ma = 0.1 default
+    cav = pkg.Cavity([sp, sp], 1e6, 0.71, storage=storage)      # Ma = 0.1 default
     prev, steps = None, 0
     while steps < 2_000_000:
         cav.step(50_000)
@@ -31,7 +32,7 @@ def test_table2_ra1e6_257():
             break
         prev = st["nu_vol"]
     cav.close()
-    print(f"steps {steps}: " + " ".join(f"{k} {st[k]:.5f}" for k in
+    print(f"{storage} steps {steps}: " + " ".join(f"{k} {st[k]:.5f}" for k in
                                         ("nu_vol", "nu_hot", "nu_mid", "re_vol", "re_rms")),
           flush=True)
     assert abs(st["nu_vol"] / ref["nu_vol"] - 1) < 2e-3
