@@ -67,7 +67,10 @@ typedef enum { ISLBM_D2Q9_D2Q5 = 2, ISLBM_D3Q19_D3Q7 = 3 } islbm_lattice;
 /* Storage type of the populations in HBM.  Arithmetic is FP32 for FP32,
  * FP16DEV and BF16DEV (deviations f - w_i and g stored in half / bfloat16;
  * FP16 scaled by 2^12, so it holds deviations up to 16 in magnitude), and
- * FP64 for FP64. */
+ * FP64 for FP64.  The time step writes FP16DEV / BF16DEV with stochastic
+ * rounding (expected stored value = the FP32 result), its random bits a hash
+ * of node, population and a device-side step counter; all other conversions
+ * round to nearest. */
 typedef enum { ISLBM_FP32 = 0, ISLBM_FP64 = 1, ISLBM_FP16DEV = 2, ISLBM_BF16DEV = 3 } islbm_storage;
 
 typedef struct {
@@ -182,8 +185,9 @@ int islbm_get_populations(islbm_ctx* ctx, double* f, double* g);
  * first.  The step counter is left unchanged. */
 int islbm_set_populations(islbm_ctx* ctx, const double* f, const double* g, int post_collision);
 
-/* Size in bytes of the raw state (both population sets in the storage type;
- * the checkpoint format of islbm_save_state / islbm_load_state). */
+/* Size in bytes of the raw state (both population sets in the storage type,
+ * then the 4-byte step counter of the stochastic rounding; the checkpoint
+ * format of islbm_save_state / islbm_load_state). */
 int islbm_state_bytes(const islbm_ctx* ctx, size_t* bytes);
 
 /* Copies the raw post-collision state (storage type, device layout) into a

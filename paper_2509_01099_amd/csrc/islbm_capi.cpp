@@ -33,6 +33,7 @@ struct islbm_ctx {
   void* wtab[3] = {nullptr, nullptr, nullptr};
   double* red = nullptr;
   double* partials = nullptr;
+  unsigned int* rctr = nullptr;  // step counters of the stochastic rounding
   int partials_cap = 0, partials_n = 0;
   bool partials_valid = false;
   double* dres = nullptr;
@@ -54,6 +55,8 @@ struct islbm_ctx {
 };
 
 static thread_local std::string g_create_error;
+
+static constexpr size_t kCtrBytes = sizeof(unsigned int);  // saved step counter
 
 static const char* kStatusText[] = {"ok",
                                     "invalid argument",
@@ -166,6 +169,7 @@ static void release(islbm_ctx* c) {
     if (w) hipFree(w);
   if (c->red) hipFree(c->red);
   if (c->partials) hipFree(c->partials);
+  if (c->rctr) hipFree(c->rctr);
   if (c->dres) hipFree(c->dres);
   if (c->hres) hipHostFree(c->hres);
   if (c->staging) hipFree(c->staging);
@@ -453,6 +457,11 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
     return bail(hipfail(c, e, "hipHostMalloc"));
   if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess)
     return bail(hipfail(c, e, "hipEventCreate"));
+  if ((e = hipMalloc(&c->rctr, 2 * sizeof(unsigned int))) != hipSuccess) return bail(hipfail(c, e, "hipMalloc(rctr)"));
+  if ((e = islbm::launch_fill_zero(c->rctr, 2 * sizeof(unsigned int), c->stream)) != hipSuccess)
+    return bail(hipfail(c, e, "fill"));
+  s.rctr = c->rctr;
+  s.rpar = 0;
   // rest state: all deviations zero (f = w, g = 0); it is its own collision
   for (int i = 0; i < 4; ++i) {
     e = islbm::launch_fill_zero(c->buf[i], i < 2 ? c->fbytes : c->gbytes, c->stream);
@@ -468,6 +477,7 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
 // One fused launch from the current buffers into the other pair.
 static hipError_t one_step(islbm_ctx* c, bool reduce) {
   const int in = c->cur, outb = c->cur ^ 1;
+  c->s.rpar = in;
   hipError_t e = islbm::launch_step(c->s, fbuf(c, in), gbuf(c, in), fbuf(c, outb), gbuf(c, outb), reduce,
                                     c->partials, c->stream);
   if (e == hipSuccess) {
@@ -490,6 +500,7 @@ static hipError_t build_graph(islbm_ctx* c) {
   if (e == hipSuccess) {
     int cur = c->cur;
     for (int i = 0; i < kGraphBatch && e == hipSuccess; ++i) {
+      c->s.rpar = cur;
       e = islbm::launch_step(c->s, fbuf(c, cur), gbuf(c, cur), fbuf(c, cur ^ 1), gbuf(c, cur ^ 1), false,
                              c->partials, cap);
       cur ^= 1;
@@ -758,26 +769,31 @@ extern "C" int islbm_fields(islbm_ctx* ctx, double* rho, double* ux, double* uy,
 
 extern "C" int islbm_state_bytes(const islbm_ctx* ctx, size_t* bytes) {
   if (!ctx || !bytes) return ISLBM_EINVAL;
-  *bytes = ctx->fbytes + ctx->gbytes;
+  *bytes = ctx->fbytes + ctx->gbytes + kCtrBytes;
   return ISLBM_OK;
 }
 
 extern "C" int islbm_save_state(islbm_ctx* ctx, void* host, size_t bytes) {
-  if (!ctx || !host || bytes < ctx->fbytes + ctx->gbytes) return ISLBM_EINVAL;
+  if (!ctx || !host || bytes < ctx->fbytes + ctx->gbytes + kCtrBytes) return ISLBM_EINVAL;
   char* h = static_cast<char*>(host);
   HIPCHECK(ctx, hipMemcpyAsync(h, fbuf(ctx, ctx->cur), ctx->fbytes, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHECK(ctx, hipMemcpyAsync(h + ctx->fbytes, gbuf(ctx, ctx->cur), ctx->gbytes, hipMemcpyDeviceToHost,
                                ctx->stream));
+  // the step counter the next launch reads (stochastic rounding of 2-byte storage)
+  HIPCHECK(ctx, hipMemcpyAsync(h + ctx->fbytes + ctx->gbytes, ctx->rctr + ctx->cur, kCtrBytes,
+                               hipMemcpyDeviceToHost, ctx->stream));
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   return ISLBM_OK;
 }
 
 extern "C" int islbm_load_state(islbm_ctx* ctx, const void* host, size_t bytes) {
-  if (!ctx || !host || bytes != ctx->fbytes + ctx->gbytes) return ISLBM_EINVAL;
+  if (!ctx || !host || bytes != ctx->fbytes + ctx->gbytes + kCtrBytes) return ISLBM_EINVAL;
   const char* h = static_cast<const char*>(host);
   HIPCHECK(ctx, hipMemcpyAsync(fbuf(ctx, ctx->cur), h, ctx->fbytes, hipMemcpyHostToDevice, ctx->stream));
   HIPCHECK(ctx, hipMemcpyAsync(gbuf(ctx, ctx->cur), h + ctx->fbytes, ctx->gbytes, hipMemcpyHostToDevice,
                                ctx->stream));
+  HIPCHECK(ctx, hipMemcpyAsync(ctx->rctr + ctx->cur, h + ctx->fbytes + ctx->gbytes, kCtrBytes,
+                               hipMemcpyHostToDevice, ctx->stream));
   HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->partials_valid = false;
   ctx->snap_valid = false;

@@ -38,6 +38,7 @@ struct Store;
 template <>
 struct Store<float> {
   using R = float;
+  static constexpr bool kDither = false;
   __device__ static float ld(const float* p) { return *p; }
   __device__ static void st(float* p, float v) { *p = v; }
   __device__ static void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
@@ -45,6 +46,7 @@ struct Store<float> {
 template <>
 struct Store<double> {
   using R = double;
+  static constexpr bool kDither = false;
   __device__ static double ld(const double* p) { return *p; }
   __device__ static void st(double* p, double v) { *p = v; }
   __device__ static void st_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
@@ -52,21 +54,63 @@ struct Store<double> {
 // FP16 holds the deviations scaled by 2^12 (an exact power of two): deviations
 // down to ~1.5e-8 stay normal numbers; |f - w| and |g| up to 16 are
 // representable.  BF16 has the FP32 exponent range and needs no scale.
+//
+// The time step stores 2-byte values with stochastic rounding (st_dither):
+// the FP32 result is rounded up with probability equal to its distance from
+// the lower neighbour in units of the spacing, using 13 (FP16) or 16 (BF16)
+// random bits added below the kept mantissa bits before truncation.  With
+// round-to-nearest, a change smaller than half a spacing is lost every step
+// and slowly driven states stall; stochastic rounding keeps the expected
+// stored value equal to the FP32 one.  Other writers (initialisation,
+// uploads) round to nearest.
 template <>
 struct Store<__half> {
   using R = float;
+  static constexpr bool kDither = true;
   static constexpr float kScale = 4096.0f, kInv = 1.0f / 4096.0f;
   __device__ static float ld(const __half* p) { return __half2float(*p) * kInv; }
   __device__ static void st(__half* p, float v) { *p = __float2half_rn(v * kScale); }
   __device__ static void st_nt(__half* p, float v) { st(p, v); }
+  __device__ static void st_dither(__half* p, float v, unsigned bits) {
+    unsigned u = __float_as_uint(v * kScale);
+    u = (u + (bits >> 19)) & ~0x1FFFu;  // exact in FP16 across its normal range
+    *p = __float2half_rn(__uint_as_float(u));
+  }
 };
 template <>
 struct Store<__hip_bfloat16> {
   using R = float;
+  static constexpr bool kDither = true;
   __device__ static float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
   __device__ static void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
   __device__ static void st_nt(__hip_bfloat16* p, float v) { st(p, v); }
+  __device__ static void st_dither(__hip_bfloat16* p, float v, unsigned bits) {
+    unsigned u = __float_as_uint(v);
+    u = (u + (bits >> 16)) & 0xFFFF0000u;  // the kept upper half is the bfloat16
+    *p = __float2bfloat16(__uint_as_float(u));
+  }
 };
+
+// 32-bit integer hash "lowbias32" (C. Wellons, "Prospecting for hash
+// functions", 2018) of node and device-side step counter; the bits of
+// population i are the top bits of that hash times a distinct odd constant
+// (multiply-shift hashing), which st_dither takes from the high end.
+__device__ __forceinline__ unsigned mix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Store of population i of a node whose hash is h0.
+template <typename S, bool NTS>
+__device__ __forceinline__ void store_pop(S* p, typename Store<S>::R v, unsigned h0, int i) {
+  if constexpr (Store<S>::kDither) Store<S>::st_dither(p, v, h0 * (unsigned(2 * i + 1) * 0x9E3779B1u));
+  else if constexpr (NTS) Store<S>::st_nt(p, v);
+  else Store<S>::st(p, v);
+}
 
 template <typename R>
 struct KArgs {
@@ -84,6 +128,10 @@ struct KArgs {
   const double* red;
   long long red_vol[3], red_mw[3], red_chot, red_ccold, red_cmv, red_cmd;
   double inv_uf, inv_dT, T0;
+  // step counters of the stochastic rounding: a launch reads rctr[rpar] and
+  // its block 0 writes rctr[rpar ^ 1] = rctr[rpar] + 1 for the next launch
+  unsigned int* rctr;
+  int rpar;
 };
 
 template <typename R>
@@ -121,7 +169,21 @@ static KArgs<R> make_args(const DevState& s) {
   a.inv_uf = s.inv_uf;
   a.inv_dT = s.inv_dT;
   a.T0 = s.T0;
+  a.rctr = s.rctr;
+  a.rpar = s.rpar;
   return a;
+}
+
+// Per-launch key of the stochastic rounding (2-byte storage only).
+template <typename S, typename R>
+__device__ __forceinline__ unsigned dither_key(const KArgs<R>& a) {
+  if constexpr (Store<S>::kDither) {
+    const unsigned base = a.rctr[a.rpar];
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.rctr[a.rpar ^ 1] = base + 1u;
+    return mix32(base * 0x85EBCA77u + 0x165667B1u);
+  } else {
+    return 0u;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -424,6 +486,7 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   using LF = typename SL::LF;
   using LG = typename SL::LG;
   __shared__ R lds[SL::total];
+  const unsigned dkey = dither_key<S>(a);
 
   const TileOrigin o = tile_origin<T>(a.n, a.tiles, a.nblocks);
   // 1. issue every global load of the tile (moving populations into staging
@@ -519,16 +582,11 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
       }
     }
     const long long c = ((long long)q.g[2] * a.n[1] + q.g[1]) * a.pitch + q.g[0];
+    const unsigned h0 = Store<S>::kDither ? mix32(unsigned(c) ^ dkey) : 0u;
 #pragma unroll
-    for (int i = 0; i < LF::Q; ++i) {
-      if constexpr (NTS) Store<S>::st_nt(fout + (long long)i * a.plane + c, d[i]);
-      else Store<S>::st(fout + (long long)i * a.plane + c, d[i]);
-    }
+    for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(fout + (long long)i * a.plane + c, d[i], h0, i);
 #pragma unroll
-    for (int i = 0; i < LG::Q; ++i) {
-      if constexpr (NTS) Store<S>::st_nt(gout + (long long)i * a.plane + c, g[i]);
-      else Store<S>::st(gout + (long long)i * a.plane + c, g[i]);
-    }
+    for (int i = 0; i < LG::Q; ++i) store_pop<S, NTS>(gout + (long long)i * a.plane + c, g[i], h0, 32 + i);
   }
   if constexpr (REDUCE) {
     const int lb = blockIdx.x;
@@ -685,6 +743,7 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
   using MS = MStage<M>;
   __shared__ R lds[SL::total];
   constexpr auto slots = std::make_integer_sequence<int, SL::N>{};
+  const unsigned dkey = dither_key<S>(a);
 
   // column and z segment of this workgroup (XCD-aware numbering as in step_kernel)
   const int b = blockIdx.x;
@@ -768,16 +827,11 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
       collide<3>(d, g, a.k, m);
       if constexpr (REDUCE) red_node(acc, a, q.g, m);
       const long long c = (long long)z * zstride + cxy;
+      const unsigned h0 = Store<S>::kDither ? mix32(unsigned(c) ^ dkey) : 0u;
 #pragma unroll
-      for (int i = 0; i < LF::Q; ++i) {
-        if constexpr (NTS) Store<S>::st_nt(fout + (long long)i * a.plane + c, d[i]);
-        else Store<S>::st(fout + (long long)i * a.plane + c, d[i]);
-      }
+      for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(fout + (long long)i * a.plane + c, d[i], h0, i);
 #pragma unroll
-      for (int i = 0; i < LG::Q; ++i) {
-        if constexpr (NTS) Store<S>::st_nt(gout + (long long)i * a.plane + c, g[i]);
-        else Store<S>::st(gout + (long long)i * a.plane + c, g[i]);
-      }
+      for (int i = 0; i < LG::Q; ++i) store_pop<S, NTS>(gout + (long long)i * a.plane + c, g[i], h0, 32 + i);
     }
     __syncthreads();
     if (more) commit_class<M, false, R>(lds, regs, 0, slots);

@@ -29,6 +29,10 @@ struct DevState {
   // (V/Delta), then chot, ccold, cmv, cmd over n[0]
   const double* red;
   long long red_vol[3], red_mw[3], red_chot, red_ccold, red_cmv, red_cmd;
+  // stochastic rounding of 2-byte storage: two device step counters; a step
+  // launch reads rctr[rpar] and writes rctr[rpar ^ 1] (rpar = buffer parity)
+  unsigned int* rctr;
+  int rpar;
 };
 
 constexpr int kRedSlots = 13;  // 8 sums, 3 maxima, 1 non-finite count, 1 sum (|u*|^2)

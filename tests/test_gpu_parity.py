@@ -219,17 +219,19 @@ def test_steady_change_matches_oracle(dim, storage, tol):
     cav.close()
 
 
-def test_checkpoint_restore_is_bitwise():
-    """run(2n) equals run(n) -> save -> new context -> restore -> run(n)."""
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_checkpoint_restore_is_bitwise(storage):
+    """run(2n) equals run(n) -> save -> new context -> restore -> run(n)
+    (for 2-byte storage the saved step counter keeps the rounding bits)."""
     meshes = [("tanh", 90, 1.5), ("tanh", 50, 1.5)]
-    a, _ = make_pair(meshes, 1e6, 0.71)
+    a, _ = make_pair(meshes, 1e6, 0.71, storage=storage)
     a.step(300)
     ref_f, ref_g = a.populations()
-    b, _ = make_pair(meshes, 1e6, 0.71)
+    b, _ = make_pair(meshes, 1e6, 0.71, storage=storage)
     b.step(150)
     blob = b.save_state()
     b.close()
-    c, _ = make_pair(meshes, 1e6, 0.71)
+    c, _ = make_pair(meshes, 1e6, 0.71, storage=storage)
     c.load_state(blob)
     c.step(150)
     cf, cg = c.populations()
