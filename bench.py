@@ -216,7 +216,7 @@ def converge(cav, max_steps: int, tol: float = 1e-9, interval: int = 2000,
         cav.step(interval)
         du, dT, _ = cav.steady_change()
         done += check
-        if done % 500000 == 0:
+        if done % (10 * check) == 0:
             _log(f"{tag} step {done} du {du:.2e} dT {dT:.2e} t={time.perf_counter() - t0:.0f}s")
         if du < tol and dT < tol:
             break
@@ -277,6 +277,33 @@ def convergence_study(Ra: float = 1e6, sizes=(257, 513, 1025), max_steps: int = 
             gci = 1.25 * abs((ff - fm) / ff) / (r ** p - 1) * 100
             rich[k] = {"p": p, "extrapolated": finf, "gci_fine_pct": gci}
         out["richardson"] = rich
+    return out
+
+
+def validation_3d(n: int = 129, Ra: float = 1e5, max_steps: int = 1_200_000,
+                  storage: str = "fp64") -> dict:
+    """Steady 3-D cavity on the paper's erf mesh (a = 1.5) run to the Sec. 3
+    steady criterion, against the Sec. 4 table values for the same mesh."""
+    import paper_2509_01099_amd as pkg
+
+    table = {(129, 1e5): {"nu_vol": 4.3406, "nu_hot": 4.3624, "nu_cold": 4.3624, "re": 39.4521}}
+    sp = pkg.islbm_mesh_spacing("erf", n, 1.5)
+    sp = sp / sp[0]
+    cav = pkg.Cavity([sp, sp, sp], Ra, PR, storage=storage)
+    steps, du, dT, secs = converge(cav, max_steps, check=20000, tag=f"{n}^3")
+    st = cav.stats()
+    cav.close()
+    out = {"workload": f"3-D cavity Ra={Ra:g} Pr=0.71, {n}^3 erf mesh a=1.5, {storage}, from rest",
+           "steps": steps, "du": du, "dT": dT, "seconds": round(secs, 1),
+           "stats": {k: st[k] for k in ("nu_vol", "nu_hot", "nu_cold", "re_vol", "re_rms")}}
+    ref = table.get((n, Ra))
+    if ref:
+        out["paper"] = ref
+        out["rel_diff"] = {"nu_vol": st["nu_vol"] / ref["nu_vol"] - 1,
+                           "nu_hot": st["nu_hot"] / ref["nu_hot"] - 1,
+                           "nu_cold": st["nu_cold"] / ref["nu_cold"] - 1,
+                           "re_rms": st["re_rms"] / ref["re"] - 1,
+                           "re_vol": st["re_vol"] / ref["re"] - 1}
     return out
 
 
@@ -431,6 +458,8 @@ def main() -> int:
                     help="grid-convergence study instead of the headline line: 2-D cavity at "
                          "this Ra on erf meshes 257/513/1025 (1e6) or 513/1025/2049, FP64, "
                          "run to the steady criterion; observed order and extrapolation")
+    ap.add_argument("--validation3d", action="store_true",
+                    help="steady 3-D cavity (129^3 erf, Ra 1e5, FP64) against the paper's table")
     ap.add_argument("--profile-mesh", choices=["2d", "3d", "3d-uniform"], default="2d",
                     help="workload of --profile: the 2-D benchmark mesh, the 3-D 256^3 tanh "
                          "mesh (Ra 1e7) or the 3-D 256^3 uniform mesh")
@@ -451,6 +480,9 @@ def main() -> int:
     n = (N_CFG, N_CFG)
     nodes = N_CFG * N_CFG
 
+    if args.validation3d:
+        print(json.dumps(validation_3d()))
+        return 0
     if args.convergence:
         sizes = (257, 513, 1025) if args.convergence < 5e6 else (513, 1025, 2049)
         print(json.dumps(convergence_study(args.convergence, sizes)))
