@@ -91,6 +91,22 @@ struct Store<__hip_bfloat16> {
   }
 };
 
+// p + off with the byte offset formed in 32 bits.  With p uniform over the
+// workgroup, the access takes a scalar base plus a 32-bit vector offset
+// instead of a 64-bit vector address (fewer address instructions).  Used by
+// the cache-resident class of launches, where it measured faster; the
+// large class keeps 64-bit addressing, which measured faster there.  The
+// cache-resident class (FP32, FP16, BF16 storage) has both population
+// buffers below 192 MB, so no offset within them reaches 2^32 bytes.
+template <typename S>
+__device__ __forceinline__ const S* at(const S* p, unsigned off) {
+  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(p) + off * unsigned(sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ S* at(S* p, unsigned off) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(p) + off * unsigned(sizeof(S)));
+}
+
 // 32-bit integer hash "lowbias32" (C. Wellons, "Prospecting for hash
 // functions", 2018) of node and device-side step counter; the bits of
 // population i are the top bits of that hash times a distinct odd constant
@@ -268,16 +284,18 @@ struct Staging {
   static constexpr int total = roff(SL::N);
 };
 
-template <int D, class T, int s, typename S, typename R>
+template <int D, class T, int s, bool OFF32, typename S, typename R>
 __device__ __forceinline__ void issue_slot(R* regs, const S* __restrict__ fin, const S* __restrict__ gin,
                                            const KArgs<R>& a, const TileOrigin& o) {
   using SL = Slots<D, T>;
   using ST = Staging<D, T>;
   constexpr int W = SL::ext(s, 0), H = SL::ext(s, 1), V = SL::size(s);
-  const S* src = (SL::isg(s) ? gin : fin) + (long long)SL::pop(s) * a.plane;
   const int ox = SL::e(s, 0) ? o.lo[0] : o.t0[0];
   const int oy = SL::e(s, 1) ? o.lo[1] : o.t0[1];
   const int oz = SL::e(s, 2) ? o.lo[2] : o.t0[2];
+  // OFF32: base at the slot's first (y, z) row, 32-bit offsets from it
+  const S* src = (SL::isg(s) ? gin : fin) + (long long)SL::pop(s) * a.plane +
+                 (OFF32 ? ((long long)oz * a.n[1] + oy) * a.pitch : 0LL);
 #pragma unroll
   for (int k = 0; k < ST::iters(s); ++k) {
     // Branch-free: positions beyond the slot or the mesh are clamped to a
@@ -291,7 +309,11 @@ __device__ __forceinline__ void issue_slot(R* regs, const S* __restrict__ fin, c
     const int gx = min(ox + lx, a.n[0] - 1);
     const int gy = min(oy + ly, a.n[1] - 1);
     const int gz = min(oz + lz, a.n[2] - 1);
-    regs[ST::roff(s) + k] = Store<S>::ld(src + ((long long)gz * a.n[1] + gy) * a.pitch + gx);
+    if constexpr (OFF32)
+      regs[ST::roff(s) + k] = Store<S>::ld(
+          at(src, (unsigned(gz - oz) * unsigned(a.n[1]) + unsigned(gy - oy)) * unsigned(a.pitch) + unsigned(gx)));
+    else
+      regs[ST::roff(s) + k] = Store<S>::ld(src + ((long long)gz * a.n[1] + gy) * a.pitch + gx);
   }
 }
 
@@ -487,13 +509,16 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   using LG = typename SL::LG;
   __shared__ R lds[SL::total];
   const unsigned dkey = dither_key<S>(a);
+  // cache-resident class with FP32 arithmetic: scalar base + 32-bit offsets
+  // (FP64 storage is always stepped with 64-bit addresses and plain stores)
+  constexpr bool OFF32 = !NTS && !std::is_same_v<S, double>;
 
   const TileOrigin o = tile_origin<T>(a.n, a.tiles, a.nblocks);
   // 1. issue every global load of the tile (moving populations into staging
   //    registers, rest populations and this thread's x weights directly)
   R regs[Staging<D, T>::total];
   [&]<int... SS>(std::integer_sequence<int, SS...>) {
-    (issue_slot<D, T, SS, S, R>(regs, fin, gin, a, o), ...);
+    (issue_slot<D, T, SS, OFF32, S, R>(regs, fin, gin, a, o), ...);
   }(std::make_integer_sequence<int, SL::N>{});
 
   const int lx = threadIdx.x % T::TX;
@@ -515,17 +540,28 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
       q.wm[0][c] = a.wtab[0][((long long)a.n[0] + q.g[0]) * 4 + c];
     }
   }
+  // node (lx, ly, lz) of the tile: tbase + toff (OFF32) or the 64-bit index
+  const long long tbase = ((long long)o.t0[2] * a.n[1] + o.t0[1]) * a.pitch;
+  auto toff = [&](int ly, int lz) {
+    return (unsigned(lz) * unsigned(a.n[1]) + unsigned(ly)) * unsigned(a.pitch) + unsigned(q.g[0]);
+  };
   R rest_f[T::NR], rest_g[T::NR];
 #pragma unroll
   for (int k = 0; k < T::NR; ++k) {
     const int row = r0 + k * T::RS;
-    const int gy = o.t0[1] + row % T::TY, gz = o.t0[2] + row / T::TY;
+    const int ly = row % T::TY, lz = row / T::TY;
+    const int gy = o.t0[1] + ly, gz = o.t0[2] + lz;
     rest_f[k] = R(0);
     rest_g[k] = R(0);
     if (xin && gy < a.n[1] && gz < a.n[2]) {
-      const long long c = ((long long)gz * a.n[1] + gy) * a.pitch + q.g[0];
-      rest_f[k] = Store<S>::ld(fin + c);
-      rest_g[k] = Store<S>::ld(gin + c);
+      if constexpr (OFF32) {
+        rest_f[k] = Store<S>::ld(at(fin + tbase, toff(ly, lz)));
+        rest_g[k] = Store<S>::ld(at(gin + tbase, toff(ly, lz)));
+      } else {
+        const long long c = ((long long)gz * a.n[1] + gy) * a.pitch + q.g[0];
+        rest_f[k] = Store<S>::ld(fin + c);
+        rest_g[k] = Store<S>::ld(gin + c);
+      }
     }
   }
   // 2. write the staged tiles to LDS
@@ -583,10 +619,19 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
     }
     const long long c = ((long long)q.g[2] * a.n[1] + q.g[1]) * a.pitch + q.g[0];
     const unsigned h0 = Store<S>::kDither ? mix32(unsigned(c) ^ dkey) : 0u;
+    if constexpr (OFF32) {
+      const unsigned cl = toff(ly, lz);
 #pragma unroll
-    for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(fout + (long long)i * a.plane + c, d[i], h0, i);
+      for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(at(fout + (tbase + (long long)i * a.plane), cl), d[i], h0, i);
 #pragma unroll
-    for (int i = 0; i < LG::Q; ++i) store_pop<S, NTS>(gout + (long long)i * a.plane + c, g[i], h0, 32 + i);
+      for (int i = 0; i < LG::Q; ++i)
+        store_pop<S, NTS>(at(gout + (tbase + (long long)i * a.plane), cl), g[i], h0, 32 + i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(fout + (long long)i * a.plane + c, d[i], h0, i);
+#pragma unroll
+      for (int i = 0; i < LG::Q; ++i) store_pop<S, NTS>(gout + (long long)i * a.plane + c, g[i], h0, 32 + i);
+    }
   }
   if constexpr (REDUCE) {
     const int lb = blockIdx.x;

@@ -121,6 +121,43 @@ def test_parity_3d_fp32_uniform_random(nz, seed):
     cav.close()
 
 
+@pytest.mark.parametrize("meshes", [
+    [("tanh", 3, 1.5), ("tanh", 3, 1.5)],                          # smallest 2-D mesh
+    [("erf", 5, 1.5), ("erf", 3, 1.5)],
+    [("tanh", 3, 1.5), ("tanh", 3, 1.5), ("tanh", 3, 1.5)],        # smallest 3-D mesh
+    [("uniform", 4, 0), ("uniform", 3, 0), ("uniform", 5, 0)],     # 3-D marching kernel
+])
+def test_parity_smallest_meshes(meshes):
+    """Three fluid nodes per axis (every node a wall node, every stencil
+    clamped), 100 steps from a seeded random state."""
+    oracle.set_threads(16)
+    cav, orc = make_pair(meshes, 1e6, 0.71, allow_unstable=1)
+    f, g = _random_state(orc, 12)
+    cav.set_populations(f, g, post_collision=False)
+    orc.set_state(f, g)
+    cav.step(100)
+    orc.run(100)
+    fp, gp = cav.populations()
+    orc.collide()
+    ofp, ogp = orc.post()
+    ef, eg = rel_f(fp, ofp), rel_g(gp, ogp)
+    print(f"{[m[1] for m in meshes]}: f {ef:.2e} g {eg:.2e}", flush=True)
+    assert ef <= 1e-5 and eg <= 1e-5
+    cav.close()
+
+
+def test_zero_steps_is_a_no_op():
+    """islbm_step(0) changes neither the state nor the time level."""
+    cav, orc = make_pair([("tanh", 40, 1.5), ("tanh", 30, 1.5)], 1e6, 0.71)
+    cav.step(7)
+    f0, g0 = cav.populations()
+    t0 = cav.t
+    cav.step(0)
+    f1, g1 = cav.populations()
+    assert cav.t == t0 and np.array_equal(f0, f1) and np.array_equal(g0, g1)
+    cav.close()
+
+
 def test_parity_3d_fp64_random():
     oracle.set_threads(16)
     cav, orc = make_pair([("tanh", 21, 1.5), ("tanh", 19, 1.5), ("tanh", 9, 1.5)], 1e7, 0.71,
