@@ -3,6 +3,7 @@
  * (gfx950, BF16 matrix cores with FP32 accumulation).
  *
  * The warm start predicts the steady velocity and temperature of the cavity
+ * (2-D: u, v, T from x, y, log10 Ra; 3-D: u, v, w, T from x, y, z, log10 Ra)
  * at an unseen Rayleigh number from a coordinate network trained on fields the
  * solver produced; the prediction sets equilibrium initial populations
  * (islbm_init_fields_device), and the solver then runs as usual.  These entry
@@ -31,6 +32,12 @@ extern "C" {
  * B is F x 3 floats.  out: bf16, n x (2F), leading dimension ldo. */
 int islbm_mlp_features(const float* p, int n, const float* B, int F, void* out, int ldo,
                        void* stream);
+
+/* The same for d inputs per point (1 <= d <= 8): p is n x d floats (ld d), B is
+ * F x d floats; out[i][f] = sin(2 pi <B_f, p_i>), out[i][F + f] = cos(...).
+ * The 3-D cavity uses d = 4 (x, y, z, log10 Ra - 7). */
+int islbm_mlp_features_d(const float* p, int n, int d, const float* B, int F, void* out, int ldo,
+                         void* stream);
 
 /* GEMM modes (A, B bf16; accumulation FP32 on the matrix cores):
  *   0 (NT): C[M][N] = sum_k A[m][k] B[n][k]    (A: M x K, B: N x K)

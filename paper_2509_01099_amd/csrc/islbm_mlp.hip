@@ -132,15 +132,16 @@ __global__ void splitk_sum_kernel(const float* __restrict__ ws, int splits, int 
   }
 }
 
-__global__ void features_kernel(const float* __restrict__ p, int n, const float* __restrict__ B, int F,
+__global__ void features_kernel(const float* __restrict__ p, int n, int d, const float* __restrict__ B, int F,
                                 __bf16* __restrict__ out, int ldo) {
   const long long total = (long long)n * F;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const long long i = e / F;
     const int f = (int)(e % F);
-    const float z = 6.283185307179586f *
-                    (B[3 * f] * p[3 * i] + B[3 * f + 1] * p[3 * i + 1] + B[3 * f + 2] * p[3 * i + 2]);
+    float dot = 0.0f;
+    for (int c = 0; c < d; ++c) dot += B[(long long)d * f + c] * p[(long long)d * i + c];
+    const float z = 6.283185307179586f * dot;
     out[i * ldo + f] = __bf16(sinf(z));
     out[i * ldo + F + f] = __bf16(cosf(z));
   }
@@ -240,11 +241,16 @@ static hipError_t gemm_launch(int M, int N, int K, const void* A, int lda, const
 
 using namespace islbm_mlp;
 
-extern "C" int islbm_mlp_features(const float* p, int n, const float* B, int F, void* out, int ldo, void* stream) {
-  if (!p || !B || !out || n <= 0 || F <= 0 || ldo < 2 * F) return -1;
-  hipLaunchKernelGGL(features_kernel, dim3(grid_for((long long)n * F)), dim3(256), 0, (hipStream_t)stream, p, n, B,
-                     F, static_cast<__bf16*>(out), ldo);
+extern "C" int islbm_mlp_features_d(const float* p, int n, int d, const float* B, int F, void* out, int ldo,
+                                    void* stream) {
+  if (!p || !B || !out || n <= 0 || d <= 0 || d > 8 || F <= 0 || ldo < 2 * F) return -1;
+  hipLaunchKernelGGL(features_kernel, dim3(grid_for((long long)n * F)), dim3(256), 0, (hipStream_t)stream, p, n, d,
+                     B, F, static_cast<__bf16*>(out), ldo);
   return status(hipGetLastError());
+}
+
+extern "C" int islbm_mlp_features(const float* p, int n, const float* B, int F, void* out, int ldo, void* stream) {
+  return islbm_mlp_features_d(p, n, 3, B, F, out, ldo, stream);
 }
 
 extern "C" int islbm_gemm_bf16(int mode, int M, int N, int K, const void* A, int lda, const void* B, int ldb,

@@ -1,7 +1,7 @@
 """Learned warm start for the cavity solver.
 
-A coordinate network maps Fourier features of (x, y, log10 Ra) to the steady
-(u*, v*, T*) of the side-heated cavity.  It is trained on steady fields that
+A coordinate network maps Fourier features of (x, y[, z], log10 Ra) to the
+steady (u*, v*[, w*], T*) of the side-heated cavity (2-D or 3-D).  It is trained on steady fields that
 the solver itself produced at a set of Rayleigh numbers; at an unseen Ra its
 prediction sets equilibrium initial populations (islbm_init_fields_device) in
 place of the cold start from rest, and the solver then runs unchanged.
@@ -29,13 +29,14 @@ def _lib():
     if not getattr(lib, "_mlp_ready", False):
         P, I, F, S = C.c_void_p, C.c_int, C.c_float, C.c_size_t
         lib.islbm_mlp_features.argtypes = [P, I, P, I, P, I, P]
+        lib.islbm_mlp_features_d.argtypes = [P, I, I, P, I, P, I, P]
         lib.islbm_gemm_bf16.argtypes = [I, I, I, I, P, I, P, I, P, I, P, I, P, P, I, I, P, S, P]
         lib.islbm_mlp_mse_grad.argtypes = [P, I, P, I, P, I, I, P, P, I, P, P]
         lib.islbm_mlp_colsum.argtypes = [P, I, I, I, P, P]
         lib.islbm_mlp_gather.argtypes = [P, I, P, I, I, P, I, P]
         lib.islbm_f32_to_bf16.argtypes = [P, P, S, P]
         lib.islbm_mlp_adam.argtypes = [P, P, P, P, P, S, F, F, F, F, F, I, P]
-        for n in ("islbm_mlp_features", "islbm_gemm_bf16", "islbm_mlp_mse_grad", "islbm_mlp_colsum",
+        for n in ("islbm_mlp_features", "islbm_mlp_features_d", "islbm_gemm_bf16", "islbm_mlp_mse_grad", "islbm_mlp_colsum",
                   "islbm_mlp_gather", "islbm_f32_to_bf16", "islbm_mlp_adam"):
             getattr(lib, n).restype = C.c_int
         lib._mlp_ready = True
@@ -56,6 +57,12 @@ def _ok(rc: int, what: str) -> None:
 def islbm_mlp_features(p, B, out, stream=None):
     n, F = p.shape[0], B.shape[0]
     _ok(_lib().islbm_mlp_features(_p(p), n, _p(B), F, _p(out), out.shape[1], stream), "features")
+
+
+def islbm_mlp_features_d(p, B, out, stream=None):
+    n, d = p.shape
+    _ok(_lib().islbm_mlp_features_d(_p(p), n, d, _p(B), B.shape[0], _p(out), out.shape[1], stream),
+        "features_d")
 
 
 def islbm_gemm_bf16(mode, M, N, K, A, lda, Bm, ldb, Cf=None, ldc=0, Cb=None, ldcb=0, bias=None,
@@ -94,8 +101,9 @@ def islbm_mlp_adam(w, g, m, v, wb, lr, t, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, st
 
 # ----------------------------------------------------------------------- model
 
-# fixed output scales: u*, v* are O(0.3) in the cavity, T* lies in [-1/2, 1/2]
-OUT_SCALE = np.array([1.0 / 0.3, 1.0 / 0.3, 2.0])
+# fixed output scales: u*, v* (, w*) are O(0.3) in the cavity, T* lies in [-1/2, 1/2]
+def out_scale(dim: int) -> np.ndarray:
+    return np.array([1.0 / 0.3] * dim + [2.0])
 
 
 @dataclass
@@ -103,8 +111,9 @@ class MLPConfig:
     n_freq: int = 32              # 2 * n_freq Fourier features
     hidden: int = 256
     depth: int = 4                # hidden layers
-    sigma: tuple = (6.0, 6.0, 1.0)  # frequency scale per input (x, y, s)
+    sigma: tuple = None           # frequency scale per input; None => 6 per axis, 1 for s
     seed: int = 0
+    dim: int = 2                  # cavity dimension: inputs (x, y[, z], s), outputs (u, v[, w], T)
 
 
 def ra_coord(Ra: float) -> float:
@@ -122,9 +131,11 @@ class WarmStartMLP:
         self.cfg = cfg
         self.device = torch.device(device)
         rng = np.random.default_rng(cfg.seed)
-        B = rng.normal(size=(cfg.n_freq, 3)) * np.asarray(cfg.sigma)[None, :]
+        self.n_in = self.n_out = cfg.dim + 1
+        sigma = cfg.sigma if cfg.sigma is not None else (6.0,) * cfg.dim + (1.0,)
+        B = rng.normal(size=(cfg.n_freq, self.n_in)) * np.asarray(sigma)[None, :]
         self.B = torch.tensor(B, dtype=torch.float32, device=self.device)
-        dims = [2 * cfg.n_freq] + [cfg.hidden] * cfg.depth + [3]
+        dims = [2 * cfg.n_freq] + [cfg.hidden] * cfg.depth + [self.n_out]
         self.dims = dims
         self.W, self.b = [], []
         for i in range(len(dims) - 1):
@@ -137,7 +148,7 @@ class WarmStartMLP:
         self.sync_bf16()
         self.adam_state = None
         self.t = 0
-        self.out_scale = torch.tensor(OUT_SCALE, dtype=torch.float32, device=self.device)
+        self.scale = out_scale(cfg.dim)
 
     # -- parameters
     def sync_bf16(self):
@@ -175,11 +186,11 @@ class WarmStartMLP:
         return self
 
     def forward(self, p):
-        """p: (n, 3) float32 device tensor of (x, y, s); returns (n, 3) float32
-        network outputs (scaled targets)."""
+        """p: (n, dim + 1) float32 device tensor of (x, y[, z], s); returns
+        (n, dim + 1) float32 outputs (u*, v*[, w*], T*)."""
         n = p.shape[0]
         self._buffers(n)
-        islbm_mlp_features(p, self.B, self._x0)
+        islbm_mlp_features_d(p, self.B, self._x0)
         h, k = self._x0, self.dims[0]
         L = len(self.W)
         for i in range(L):
@@ -194,7 +205,7 @@ class WarmStartMLP:
         return self._Z[L - 1]
 
     def backward(self, dout_b, dout_f, gW, gb, ws):
-        """Backpropagates dL/d(out) (bf16 and f32 copies, n x 3) into gW / gb."""
+        """Backpropagates dL/d(out) (bf16 and f32 copies, n x outputs) into gW / gb."""
         n = dout_b.shape[0]
         L = len(self.W)
         dzb, dzf = dout_b, dout_f
@@ -211,15 +222,17 @@ class WarmStartMLP:
 
     # -- training
     def train(self, inputs, targets, steps: int = 3000, batch: int = 8192, lr: float = 2e-3,
-              seed: int = 1, weights=(1.0, 1.0, 1.0), log_every: int = 0):
-        """inputs (N, 3) float32, targets (N, 3) float32 (u*, v*, T*), on the
-        device.  Returns the loss history (every log_every steps)."""
+              seed: int = 1, weights=None, log_every: int = 0):
+        """inputs (N, dim + 1) float32, targets (N, dim + 1) float32
+        (u*, v*[, w*], T*), on the device.  Returns the loss history (every
+        log_every steps)."""
         torch = self.torch
         N = inputs.shape[0]
-        # the network outputs (u*, v*, T*) directly; the loss weights w_j =
-        # weights_j * OUT_SCALE_j^2 make it the MSE of O(1)-scaled outputs
-        w = torch.tensor(np.asarray(weights) * OUT_SCALE ** 2, dtype=torch.float32,
-                         device=self.device)
+        ni, no = self.n_in, self.n_out
+        weights = np.ones(no) if weights is None else np.asarray(weights)
+        # the network outputs (u*, v*[, w*], T*) directly; the loss weights
+        # w_j = weights_j * scale_j^2 make it the MSE of O(1)-scaled outputs
+        w = torch.tensor(weights * self.scale ** 2, dtype=torch.float32, device=self.device)
         if self.adam_state is None:
             self.adam_state = [(torch.zeros_like(W), torch.zeros_like(W), torch.zeros_like(b),
                                 torch.zeros_like(b)) for W, b in zip(self.W, self.b)]
@@ -227,10 +240,10 @@ class WarmStartMLP:
         gb = [torch.empty_like(b) for b in self.b]
         ws = torch.empty(4 * 256 * 256 * ((batch + 1023) // 1024) + 1024, dtype=torch.float32,
                          device=self.device)
-        pb = torch.empty((batch, 3), dtype=torch.float32, device=self.device)
-        tb = torch.empty((batch, 3), dtype=torch.float32, device=self.device)
-        dof = torch.empty((batch, 3), dtype=torch.float32, device=self.device)
-        dob = torch.empty((batch, 3), dtype=torch.bfloat16, device=self.device)
+        pb = torch.empty((batch, ni), dtype=torch.float32, device=self.device)
+        tb = torch.empty((batch, no), dtype=torch.float32, device=self.device)
+        dof = torch.empty((batch, no), dtype=torch.float32, device=self.device)
+        dob = torch.empty((batch, no), dtype=torch.bfloat16, device=self.device)
         loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         rng = np.random.default_rng(seed)
         hist = []
@@ -252,7 +265,7 @@ class WarmStartMLP:
         return hist
 
     def predict(self, p):
-        """(n, 3) inputs -> (n, 3) float32 (u*, v*, T*) on the device."""
+        """(n, dim + 1) inputs -> (n, dim + 1) float32 (u*, v*[, w*], T*) on the device."""
         return self.forward(p)
 
 
@@ -270,18 +283,20 @@ def mesh_spacing(kind: str = "erf", n: int = 513, a: float = 1.5) -> np.ndarray:
     return sp / sp[0]
 
 
-def node_inputs(sp: np.ndarray, Ra: float, sub: int = 1) -> np.ndarray:
-    """Network inputs (x*, y*, s) of the mesh nodes (square mesh with spacings
-    sp on both axes), x* and y* measured from the walls in units of the
-    wall-to-wall height; every sub-th node per axis; rows in x-fastest order."""
+def node_inputs(sp: np.ndarray, Ra: float, sub: int = 1, dim: int = 2) -> np.ndarray:
+    """Network inputs (x*, y*[, z*], s) of the mesh nodes (square / cubic
+    mesh with spacings sp on every axis), coordinates measured from the walls
+    in units of the wall-to-wall extent; every sub-th node per axis; rows in
+    x-fastest order."""
     X = np.concatenate([[0.0], np.cumsum(sp)])
     wall0 = 0.5 * (X[0] + X[1])
     H = 0.5 * (X[-1] + X[-2]) - wall0
     c = (X[1:-1] - wall0) / H
     c = c[::sub]
-    yy, xx = np.meshgrid(c, c, indexing="ij")
-    s = np.full(xx.size, ra_coord(Ra))
-    return np.column_stack([xx.ravel(), yy.ravel(), s]).astype(np.float32)
+    grids = np.meshgrid(*([c] * dim), indexing="ij")      # slowest axis first
+    cols = [g.ravel() for g in reversed(grids)]           # x, y[, z]
+    s = np.full(cols[0].size, ra_coord(Ra))
+    return np.column_stack(cols + [s]).astype(np.float32)
 
 
 def steps_within(history, ref: float, tol: float = 1e-3) -> int | None:
@@ -337,9 +352,10 @@ def steps_to_steady(history, tol: float = 1e-9):
 
 
 def fields_star(cav, uf: float) -> np.ndarray:
-    """(n, 3) float32 (u*, v*, T*) of a 2-D cavity (x-fastest node order)."""
+    """(n, dim + 1) float32 (u*, v*[, w*], T*) of a cavity (x-fastest node order)."""
     f = cav.fields()
-    return np.column_stack([f["ux"].ravel() / uf, f["uy"].ravel() / uf, f["T"].ravel()]).astype(np.float32)
+    vel = [f[k].ravel() / uf for k in ("ux", "uy", "uz")[:cav.dim]]
+    return np.column_stack(vel + [f["T"].ravel()]).astype(np.float32)
 
 
 def predict_init(net: "WarmStartMLP", cav, sp: np.ndarray, Ra: float, uf: float) -> None:
@@ -349,11 +365,12 @@ def predict_init(net: "WarmStartMLP", cav, sp: np.ndarray, Ra: float, uf: float)
 
     from . import islbm_init_fields_device
 
-    p = torch.tensor(node_inputs(sp, Ra), device=net.device)
+    p = torch.tensor(node_inputs(sp, Ra, dim=cav.dim), device=net.device)
     out = net.predict(p)
     u = (out[:, 0] * uf).double().contiguous()
     v = (out[:, 1] * uf).double().contiguous()
-    T = out[:, 2].double().contiguous()
+    w = (out[:, 2] * uf).double().contiguous() if cav.dim == 3 else None
+    T = out[:, cav.dim].double().contiguous()
     torch.cuda.synchronize()
-    islbm_init_fields_device(cav.ctx, u, v, None, T)
-    cav.sync()  # u, v, T are released when this returns
+    islbm_init_fields_device(cav.ctx, u, v, w, T)
+    cav.sync()  # u, v, w, T are released when this returns

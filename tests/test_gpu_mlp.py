@@ -135,3 +135,19 @@ def test_training_fits_a_smooth_field():
                      log_every=50)
     print(hist, flush=True)
     assert hist[-1][1] < 0.05 * hist[0][1]
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_features_any_input_dimension(d):
+    """Fourier features of d inputs (the 3-D warm start uses d = 4) against
+    the FP64 reference, to bfloat16 resolution."""
+    from paper_2509_01099_amd.warmstart import islbm_mlp_features_d
+
+    rng = np.random.default_rng(d)
+    n, F = 777, 32
+    p = rng.random((n, d)).astype(np.float32)
+    B = (rng.normal(size=(F, d)) * 3).astype(np.float32)
+    out = torch.empty((n, 2 * F), dtype=torch.bfloat16, device="cuda")
+    islbm_mlp_features_d(_dev(p, torch.float32), _dev(B, torch.float32), out)
+    ref = mlp.features(p.astype(np.float64), B.astype(np.float64))
+    assert np.abs(out.float().cpu().double().numpy() - ref).max() <= 2 ** -8 + 1e-5

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 
 def _progress(tag):
     def log(done, hist):
-        if done % 100_000 == 0:
+        if done % 50_000 == 0:
             print(f"{tag}: {done} steps, Nu_hot {hist[-1][-1][1]:.5f}", flush=True)
     return log
 
@@ -52,6 +52,44 @@ def test_warm_start_saves_steps():
     warm_cav.close()
     cs, ws = W.steps_within(cold, ref), W.steps_within(warm, ref)
     print(f"loss {losses[0][1]:.3e} -> {losses[-1][1]:.3e}; cold {cs} steps, warm {ws} steps, "
+          f"Nu_hot steady {ref:.5f}, warm end {warm[-1][1]:.5f}", flush=True)
+    assert cs is not None and ws is not None
+    assert ws < cs
+    assert abs(warm[-1][1] - ref) <= 1e-3 * ref
+
+
+def test_warm_start_saves_steps_3d():
+    """The same in 3-D: (x, y, z, log10 Ra) -> (u, v, w, T) on a 33^3 erf mesh,
+    five training Rayleigh numbers in [1.2e5, 2e6], held-out Ra = 7e5."""
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    sp = W.mesh_spacing("erf", 33, 1.5)
+    train_ra = [1.2e5, 2.5e5, 5e5, 1e6, 2e6]
+    test_ra = 7e5
+    steps, chunk = 300_000, 5_000
+    uf = 0.1 / 3 ** 0.5
+    cavs = [pkg.Cavity([sp, sp, sp], ra, 0.71, storage="fp64", use_torch_buffers=False,
+                       own_stream=True) for ra in train_ra + [test_ra]]
+    hist = W.run_concurrent(cavs, steps, chunk, log=_progress("cold 3d"))
+    inputs = np.concatenate([W.node_inputs(sp, ra, dim=3) for ra in train_ra])
+    targets = np.concatenate([W.fields_star(c, uf) for c in cavs[:-1]])
+    assert inputs.shape[1] == 4 and targets.shape[1] == 4
+    cold = [(h[0], h[1]) for h in hist[-1]]
+    ref = cold[-1][1]
+    for c in cavs:
+        c.close()
+    net = W.WarmStartMLP(W.MLPConfig(dim=3))
+    losses = net.train(torch.tensor(inputs, device="cuda"), torch.tensor(targets, device="cuda"),
+                       steps=1500, batch=4096, log_every=500)
+    warm_cav = pkg.Cavity([sp, sp, sp], test_ra, 0.71, storage="fp64", use_torch_buffers=False,
+                          own_stream=True)
+    W.predict_init(net, warm_cav, sp, test_ra, uf)
+    warm = [(h[0], h[1]) for h in W.run_concurrent([warm_cav], steps, chunk,
+                                                   log=_progress("warm 3d"))[0]]
+    warm_cav.close()
+    cs, ws = W.steps_within(cold, ref), W.steps_within(warm, ref)
+    print(f"3d: loss {losses[0][1]:.3e} -> {losses[-1][1]:.3e}; cold {cs} steps, warm {ws} steps, "
           f"Nu_hot steady {ref:.5f}, warm end {warm[-1][1]:.5f}", flush=True)
     assert cs is not None and ws is not None
     assert ws < cs
