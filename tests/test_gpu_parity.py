@@ -79,6 +79,27 @@ def test_parity_2d_fp32_from_rest_cfg1_mesh():
     cav.close()
 
 
+def test_parity_2d_cosine256_ra1e8_subrun():
+    """The 256^2 subrun of the benchmark workload (cosine mesh, Ra = 1e8,
+    Pr = 0.71, FP32, u_f at the a_T <= 1 limit as in the benchmark) against
+    the FP64 oracle: 2000 steps from rest."""
+    oracle.set_threads(16)
+    sp = lu_spacings("cosine", 256, 0)
+    H = coords(sp)
+    H = 0.5 * (H[-1] + H[-2]) - 0.5 * (H[0] + H[1])
+    uf = min(0.1 / 3 ** 0.5, 5.0 / (20.0 * 3 ** 0.5) * (1e8 * 0.71) ** 0.5 / H)
+    cav, orc = make_pair([("cosine", 256, 0), ("cosine", 256, 0)], 1e8, 0.71, u_f=uf)
+    cav.step(100)
+    orc.run(100)
+    _compare(cav, orc, 1e-5, 1e-4, "2d fp32 cosine 256 Ra 1e8, 100 steps")
+    cav.step(1900)
+    orc.run(1900)
+    # FP32 rounding accumulates like a random walk: the 100-step population
+    # bar grows by sqrt(2000 / 100)
+    _compare(cav, orc, 1e-5 * 20 ** 0.5, 1e-4, "2d fp32 cosine 256 Ra 1e8, 2000 steps")
+    cav.close()
+
+
 def test_parity_2d_fp64_cfg1_full_run():
     """The small 2-D workload in full: 64^2 cosine, Ra = 1e6, Pr = 0.71,
     u_f = 0.1, FP64, 20000 steps from rest."""
