@@ -159,31 +159,34 @@ static void lagrange3_deriv(const double* p, double xd, double* d) {
   d[2] = ((xd - p[0]) + (xd - p[1])) / ((p[2] - p[0]) * (p[2] - p[1]));
 }
 
+// Frees everything the context owns.  Errors are ignored on purpose: this
+// runs on teardown paths where nothing useful can be done with them.
 static void release(islbm_ctx* c) {
   if (!c) return;
-  if (c->graph) hipGraphExecDestroy(c->graph);
+  auto dfree = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
   if (c->own_buf)
-    for (auto& b : c->buf)
-      if (b) hipFree(b);
-  for (auto& w : c->wtab)
-    if (w) hipFree(w);
-  if (c->red) hipFree(c->red);
-  if (c->partials) hipFree(c->partials);
-  if (c->rctr) hipFree(c->rctr);
-  if (c->dres) hipFree(c->dres);
-  if (c->hres) hipHostFree(c->hres);
-  if (c->staging) hipFree(c->staging);
-  if (c->fields_dev) hipFree(c->fields_dev);
-  if (c->snap) hipFree(c->snap);
-  if (c->snap_part) hipFree(c->snap_part);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    for (auto& b : c->buf) dfree(b);
+  for (auto& w : c->wtab) dfree(w);
+  dfree(c->red);
+  dfree(c->partials);
+  dfree(c->rctr);
+  dfree(c->dres);
+  if (c->hres) (void)hipHostFree(c->hres);
+  dfree(c->staging);
+  dfree(c->fields_dev);
+  dfree(c->snap);
+  dfree(c->snap_part);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
 extern "C" void islbm_destroy(islbm_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   release(ctx);
   delete ctx;
 }
@@ -394,9 +397,8 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
     return fail(nullptr, ISLBM_EDEVICE, "no HIP device");
   }
   int dev = 0;
-  hipGetDevice(&dev);
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
     delete c;
     return fail(nullptr, ISLBM_EDEVICE, "the current device is not gfx950");
   }
@@ -509,8 +511,8 @@ static hipError_t build_graph(islbm_ctx* c) {
     if (e == hipSuccess) e = e2;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-  if (g) hipGraphDestroy(g);
-  hipStreamDestroy(cap);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
   if (e == hipSuccess) c->graph_steps = c->cur;  // buffer parity the graph starts from
   else c->graph = nullptr;
   return e;
@@ -522,7 +524,7 @@ static int enqueue_steps(islbm_ctx* c, long long nsteps) {
   if (!c->no_graph && plain >= 2 * kGraphBatch) {
     if (!c->graph || c->graph_steps != c->cur) {
       if (c->graph) {
-        hipGraphExecDestroy(c->graph);
+        (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
       }
       if (build_graph(c) != hipSuccess) c->no_graph = 1;
@@ -740,7 +742,7 @@ extern "C" int islbm_init_fields(islbm_ctx* ctx, const double* ux, const double*
     rc = islbm_init_fields_device(ctx, dev, dev + ctx->nn, ctx->dim == 3 ? dev + 3 * (size_t)ctx->nn : nullptr,
                                   dev + 2 * (size_t)ctx->nn);
   hipError_t e = hipStreamSynchronize(ctx->stream);
-  hipFree(dev);
+  (void)hipFree(dev);
   if (rc == ISLBM_OK && e != hipSuccess) rc = hipfail(ctx, e, "hipStreamSynchronize");
   return rc;
 }
