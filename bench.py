@@ -311,8 +311,68 @@ def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def _ws_setup(n: int):
+    from paper_2509_01099_amd import warmstart as W
+
+    return W.mesh_spacing("erf", n, 1.5), W.draw_ra(40), 0.1 / 3 ** 0.5
+
+
+def _ws_run(sp, ras, uf, steps, ids, st, t0, init=None, tag="cold"):
+    """Runs the cavities of Ra indices `ids` concurrently (own streams) from
+    rest or from the network's prediction; histories carry (step, Nu_hot,
+    <Nu>, Re_rms, du, dT) every 20 000 steps."""
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    cavs = [pkg.Cavity([sp, sp], float(ras[i]), PR, storage=st, use_torch_buffers=False,
+                       own_stream=True) for i in ids]
+    init_nu = []
+    if init is not None:
+        for i, c in zip(ids, cavs):
+            W.predict_init(init, c, sp, float(ras[i]), uf)
+            init_nu.append(c.stats()["nu_hot"])
+
+    def log(done, h):
+        if done % 200000 == 0:
+            _log(f"{tag} {st} Ra#{ids[0]}..{ids[-1]} step {done} t={time.perf_counter() - t0:.0f}s "
+                 f"nu_hot={[round(x[-1][1], 4) for x in h]}")
+
+    hs = W.run_concurrent(cavs, steps, 20000, log=log, steady_interval=2000)
+    return cavs, hs, init_nu
+
+
+def warmstart_cold(steps: int, n: int, ids, storage: str = "fp64", n_train: int = 32,
+                   sub: int = 2, group: int = 16, out_path: str | None = None):
+    """Cold solves from rest of the Ra indices `ids` (`group` at a time);
+    returns their histories and, for training indices, the steady fields at
+    every sub-th node (optionally written to out_path as .npz)."""
+    import numpy as np
+
+    from paper_2509_01099_amd import warmstart as W
+
+    sp, ras, uf = _ws_setup(n)
+    t0 = time.perf_counter()
+    hist, fields = {}, {}
+    for b in range(0, len(ids), group):
+        part = list(ids[b:b + group])
+        cavs, hs, _ = _ws_run(sp, ras, uf, steps, part, storage, t0)
+        for i, c, h in zip(part, cavs, hs):
+            hist[i] = h
+            if i < n_train:
+                fields[i] = W.fields_star(c, uf).reshape(n, n, 3)[::sub, ::sub].reshape(-1, 3)
+            c.close()
+    if out_path:
+        tr = sorted(fields)
+        np.savez_compressed(out_path, ids=np.array(sorted(hist)), n=n, steps=steps, sub=sub,
+                            hist=np.array([hist[i] for i in sorted(hist)], dtype=np.float64),
+                            train_ids=np.array(tr, dtype=np.int64),
+                            fields=np.array([fields[i] for i in tr], dtype=np.float16))
+    return hist, fields
+
+
 def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8,
-                    storage: str = "fp64", train_steps: int = 6000, sub: int = 2) -> dict:
+                    storage: str = "fp64", train_steps: int = 6000, sub: int = 2,
+                    data_dir: str | None = None, warm_steps: int | None = None) -> dict:
     """Learned warm start on the 2-D cavity (n^2 erf mesh a = 1.5, Pr = 0.71,
     Ma = 0.1) at seeded log-uniform Ra in [1e6, 1e8].  Cold solves from rest
     (16 cavities at a time, each on its own stream) give the training fields
@@ -320,48 +380,36 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
     trained on the first n_train; the n_test held-out cavities are then
     started from its prediction.  Criterion: steps until Nu_hot stays within
     1e-3 of the cold-start steady value.  The same held-out cases are also
-    run with FP32 storage (cold and warm) against the same reference."""
+    run with FP32 storage (cold and warm) against the same reference.  With
+    data_dir, the cold solves are read from the .npz files that
+    `--ws-phase cold` wrote there instead of being run.  warm_steps (default
+    steps) bounds the warm runs; a run that never meets the criterion counts
+    as `steps`."""
+    import glob
+
     import numpy as np
     import torch
 
-    import paper_2509_01099_amd as pkg
     from paper_2509_01099_amd import warmstart as W
 
-    sp = W.mesh_spacing("erf", n, 1.5)
-    ras = W.draw_ra(n_train + n_test)
-    uf = 0.1 / 3 ** 0.5
-    chunk = 20000
+    sp, ras, uf = _ws_setup(n)
     t0 = time.perf_counter()
-
-    def run(ids, st, init=None, tag="cold"):
-        cavs = [pkg.Cavity([sp, sp], float(ras[i]), PR, storage=st, use_torch_buffers=False,
-                           own_stream=True) for i in ids]
-        init_nu = []
-        if init is not None:
-            for i, c in zip(ids, cavs):
-                W.predict_init(init, c, sp, float(ras[i]), uf)
-                init_nu.append(c.stats()["nu_hot"])
-
-        def log(done, h):
-            if done % 200000 == 0:
-                _log(f"{tag} {st} Ra#{ids[0]}..{ids[-1]} step {done} t={time.perf_counter() - t0:.0f}s "
-                     f"nu_hot={[round(x[-1][1], 4) for x in h]}")
-
-        t = time.perf_counter()
-        hs = W.run_concurrent(cavs, steps, chunk, log=log, steady_interval=2000)
-        return cavs, hs, init_nu
-
-    hist, inputs, targets = {}, [], []
     ids = list(range(n_train + n_test))
-    for b in range(0, len(ids), 16):
-        cavs, hs, _ = run(ids[b:b + 16], storage)
-        for i, c, h in zip(ids[b:b + 16], cavs, hs):
-            hist[i] = h
-            if i < n_train:
-                f = W.fields_star(c, uf).reshape(n, n, 3)[::sub, ::sub].reshape(-1, 3)
-                inputs.append(W.node_inputs(sp, float(ras[i]), sub))
-                targets.append(f)
-            c.close()
+    if data_dir:
+        hist, fields = {}, {}
+        for path in sorted(glob.glob(os.path.join(data_dir, f"ws{n}_cold_*.npz"))):
+            d = np.load(path)
+            assert int(d["n"]) == n and int(d["steps"]) == steps and int(d["sub"]) == sub, path
+            for i, h in zip(d["ids"], d["hist"]):
+                hist[int(i)] = [tuple(r) for r in h]
+            for i, f in zip(d["train_ids"], d["fields"]):
+                fields[int(i)] = f.astype(np.float32)
+        missing = [i for i in ids if i not in hist]
+        assert not missing, f"cold solves missing for Ra indices {missing}"
+    else:
+        hist, fields = warmstart_cold(steps, n, ids, storage, n_train, sub)
+    inputs = [W.node_inputs(sp, float(ras[i]), sub) for i in range(n_train)]
+    targets = [fields[i] for i in range(n_train)]
     ref = {i: hist[i][-1][1] for i in ids}
     cold_steady = {i: W.steps_to_steady(hist[i]) for i in ids}
     # how settled the cold references are: change over the last 10 % of the run
@@ -391,13 +439,14 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
     runs, init_nu = {}, {}
     for st in (storage, "fp32"):
         if st != storage:
-            cavs, hs, _ = run(test, st, tag="cold")
+            cavs, hs, _ = _ws_run(sp, ras, uf, steps, test, st, t0, tag="cold")
             runs[(st, "cold")] = hs
             for c in cavs:
                 c.close()
         else:
             runs[(st, "cold")] = [hist[i] for i in test]
-        cavs, hs, init_nu[st] = run(test, st, init=net, tag="warm")
+        cavs, hs, init_nu[st] = _ws_run(sp, ras, uf, warm_steps or steps, test, st, t0, init=net,
+                                        tag="warm")
         runs[(st, "warm")] = hs
         for c in cavs:
             c.close()
@@ -420,7 +469,7 @@ def warmstart_study(steps: int, n: int = 257, n_train: int = 32, n_test: int = 8
     out = {"study": f"learned warm start, 2-D cavity {n}^2 erf (a=1.5), Pr 0.71, Ma 0.1, "
                     f"{n_train} training / {n_test} held-out Ra log-uniform in [1e6, 1e8]",
            "criterion": "steps until Nu_hot stays within 1e-3 of the cold-start steady value "
-                        f"({storage} storage, {steps} steps)",
+                        f"({storage} storage, {steps} cold / {warm_steps or steps} warm steps)",
            "cold_reference_settle_last10pct": settle,
            "steady_criterion": "Sec. 3: relative change of u and T over 2000 steps below 1e-9",
            "cold_steps_to_steady_criterion_all": [cold_steady[i] for i in ids],
@@ -454,6 +503,16 @@ def main() -> int:
                     help="learned warm start study instead of the headline line: cold solves "
                          "of STEPS steps give the training fields, then warm and cold starts "
                          "are compared on held-out Rayleigh numbers")
+    ap.add_argument("--ws-n", type=int, default=257, help="warm-start mesh size (erf, a=1.5)")
+    ap.add_argument("--ws-phase", choices=["all", "cold", "eval"], default="all",
+                    help="'cold' runs the cold solves of one batch of Ra indices and writes "
+                         "gpurun_out/ws<n>_cold_<batch>.npz; 'eval' reads those files from "
+                         "--ws-dir and does training and the warm/cold comparison")
+    ap.add_argument("--ws-batch", type=int, default=0)
+    ap.add_argument("--ws-batch-size", type=int, default=8)
+    ap.add_argument("--ws-dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--ws-warm-steps", type=int, default=0,
+                    help="steps of the warm runs (default: as many as the cold solves)")
     ap.add_argument("--convergence", type=float, default=0.0, metavar="RA",
                     help="grid-convergence study instead of the headline line: 2-D cavity at "
                          "this Ra on erf meshes 257/513/1025 (1e6) or 513/1025/2049, FP64, "
@@ -488,7 +547,19 @@ def main() -> int:
         print(json.dumps(convergence_study(args.convergence, sizes)))
         return 0
     if args.warmstart:
-        print(json.dumps(warmstart_study(args.warmstart)))
+        if args.ws_phase == "cold":
+            ids = list(range(40))[args.ws_batch * args.ws_batch_size:
+                                  (args.ws_batch + 1) * args.ws_batch_size]
+            out_dir = os.path.join(ROOT, "gpurun_out")
+            os.makedirs(out_dir, exist_ok=True)
+            path = os.path.join(out_dir, f"ws{args.ws_n}_cold_{args.ws_batch}.npz")
+            hist, _ = warmstart_cold(args.warmstart, args.ws_n, ids, out_path=path)
+            print(json.dumps({"phase": "cold", "ids": ids, "file": path,
+                              "final_nu_hot": [hist[i][-1][1] for i in ids]}))
+            return 0
+        print(json.dumps(warmstart_study(args.warmstart, n=args.ws_n,
+                                         data_dir=args.ws_dir if args.ws_phase == "eval" else None,
+                                         warm_steps=args.ws_warm_steps or None)))
         return 0
     if args.precision:
         print(json.dumps(precision_study(args.precision)))
