@@ -502,3 +502,35 @@ def test_steady_change_scaling_and_fixed_point():
     du3, _ = oracle.steady_change(f, h)
     assert du3 == pytest.approx(f["uz"].size / np.sum(np.sqrt(f["ux"] ** 2 + f["uy"] ** 2
                                                               + f["uz"] ** 2)), rel=1e-12)
+
+
+@pytest.mark.parametrize("dim,kind", [(2, "tanh"), (3, "erf")])
+def test_reductions_of_a_uniform_state(dim, kind):
+    """Closed forms of the Sec. 3 / Sec. 4 averages for a state of uniform
+    density 1, uniform velocity u0 and T = T0 (no buoyancy): the midpoint
+    weights tile the cavity, so <Re> = sqrt(Ra/Pr) |u0|/u_f exactly (rms and
+    mean alike), the (u, v) Reynolds number drops w, the peak components are
+    |u0_a|/u_f, <Nu> = 1 (no convective flux), and the mass is the
+    wall-to-wall volume in lattice units."""
+    ns = (14, 11, 9)[:dim]
+    xs = [lu(kind, n) for n in ns]
+    Ra, Pr = 1e6, 0.71
+    o = oracle.Oracle(xs, Ra, Pr)
+    uf = o.params["uf"]
+    u0 = np.array([0.011, -0.007, 0.004][:dim])
+    e, w, _ = oracle.lattice(dim, 0)
+    feq = textbook_feq(e, w, 1.0, u0)
+    f = np.broadcast_to(feq.reshape((-1,) + (1,) * dim), (len(w),) + o.shape).copy()
+    g = np.zeros((o.qg,) + o.shape)
+    o.set_state(f, g)
+    st = o.stats()
+    speed = np.linalg.norm(u0) / uf
+    assert st["re_vol"] == pytest.approx(np.sqrt(Ra / Pr) * speed, rel=1e-12)
+    assert st["re_rms"] == pytest.approx(np.sqrt(Ra / Pr) * speed, rel=1e-12)
+    assert st["re_uv"] == pytest.approx(np.sqrt(Ra / Pr) * np.linalg.norm(u0[:2]) / uf, rel=1e-12)
+    for k, key in enumerate(("umax", "vmax", "wmax")[:dim]):
+        assert st[key] == pytest.approx(abs(u0[k]) / uf, rel=1e-12)
+    assert st["nu_vol"] == pytest.approx(1.0, abs=1e-12)
+    vol = np.prod([(0.5 * (x[-1] + x[-2]) - 0.5 * (x[0] + x[1])) / (x[1] - x[0]) for x in xs])
+    assert st["mass"] == pytest.approx(vol, rel=1e-12)
+    assert st["rho_sum"] == pytest.approx(np.prod(ns), rel=1e-12)
