@@ -141,8 +141,10 @@ int islbm_create(islbm_ctx** out, int lattice, const int n[3],
                  const double* const spacing[3], double Ra, double Pr,
                  const islbm_options* opt);
 
-/* Enqueues nsteps fused time steps (nsteps >= 0).  The last one also writes
- * the FP64 reduction partials used by islbm_nu_re.  Asynchronous. */
+/* Enqueues nsteps fused time steps (nsteps >= 0; 0 changes nothing).  The
+ * last one also writes the FP64 reduction partials used by islbm_nu_re.
+ * Runs of at least 128 plain steps are replayed in batches of 64 through a
+ * HIP graph that the context captures on first use.  Asynchronous. */
 int islbm_step(islbm_ctx* ctx, long long nsteps);
 
 /* Macroscopic fields at the current time level (pre-collision moments:
@@ -182,7 +184,7 @@ int islbm_get_populations(islbm_ctx* ctx, double* f, double* g);
 /* Sets the state from host arrays.  post_collision = 1: the arrays are
  * post-collision populations and are stored as given (checkpoint restore);
  * 0: they are pre-collision populations f(x,t), g(x,t) and are collided
- * first.  The step counter is left unchanged. */
+ * first.  The time level is left unchanged. */
 int islbm_set_populations(islbm_ctx* ctx, const double* f, const double* g, int post_collision);
 
 /* Size in bytes of the raw state (both population sets in the storage type,
