@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E peak
 N_CFG = 1024
 RA, PR = 1e8, 0.71
-BYTES_PER_LU = {2: {"fp32": 112, "fp64": 224, "fp16": 56, "bf16": 56},
-                3: {"fp32": 208, "fp64": 416, "fp16": 104, "bf16": 104}}
+BYTES_PER_LU = {2: {"fp32": 112, "fp64": 224, "fp16": 56, "bf16": 56, "fp32sr": 112},
+                3: {"fp32": 208, "fp64": 416, "fp16": 104, "bf16": 104, "fp32sr": 208}}
 KERNEL_SOURCES = ("paper_2509_01099_amd/csrc/islbm_kernels.hip",
                   "paper_2509_01099_amd/csrc/islbm_lattice.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_cosine1024_traffic.json")
@@ -126,7 +126,7 @@ def precision_study(steps: int, n: int = 384, steady_steps: int = 1_600_000) -> 
     import paper_2509_01099_amd as pkg
     from paper_2509_01099_amd import warmstart as W
 
-    kinds = ("fp64", "fp32", "fp16", "bf16")
+    kinds = ("fp64", "fp32", "fp16", "bf16", "fp32sr")
     keys = ("nu_vol", "nu_hot", "nu_cold", "re_vol", "re_rms", "umax", "vmax", "wmax")
     out = {"throughput": {}, "transient": {}, "steady": {}}
     for st in kinds:

@@ -67,11 +67,17 @@ typedef enum { ISLBM_D2Q9_D2Q5 = 2, ISLBM_D3Q19_D3Q7 = 3 } islbm_lattice;
 /* Storage type of the populations in HBM.  Arithmetic is FP32 for FP32,
  * FP16DEV and BF16DEV (deviations f - w_i and g stored in half / bfloat16;
  * FP16 scaled by 2^12, so it holds deviations up to 16 in magnitude), and
- * FP64 for FP64.  The time step writes FP16DEV / BF16DEV with stochastic
- * rounding (expected stored value = the FP32 result), its random bits a hash
- * of node, population and a device-side step counter; all other conversions
- * round to nearest. */
-typedef enum { ISLBM_FP32 = 0, ISLBM_FP64 = 1, ISLBM_FP16DEV = 2, ISLBM_BF16DEV = 3 } islbm_storage;
+ * FP64 for FP64 and FP32SR (FP32 storage, FP64 arithmetic).  The time step
+ * writes FP16DEV / BF16DEV / FP32SR with stochastic rounding (expected stored
+ * value = the unrounded result), its random bits a hash of node, population
+ * and a device-side step counter; all other conversions round to nearest. */
+typedef enum {
+  ISLBM_FP32 = 0,
+  ISLBM_FP64 = 1,
+  ISLBM_FP16DEV = 2,
+  ISLBM_BF16DEV = 3,
+  ISLBM_FP32SR = 4
+} islbm_storage;
 
 typedef struct {
   double u_f;            /* free-fall velocity in lattice units per step; 0 => Ma = 0.1,

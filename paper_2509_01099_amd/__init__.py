@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libislbm.so")
 ISLBM_OK, ISLBM_EINVAL, ISLBM_EMESH, ISLBM_EPARAM = 0, -1, -2, -3
 ISLBM_ENOMEM, ISLBM_EDEVICE, ISLBM_ENONFINITE = -4, -5, -6
 ISLBM_D2Q9_D2Q5, ISLBM_D3Q19_D3Q7 = 2, 3
-ISLBM_FP32, ISLBM_FP64, ISLBM_FP16DEV, ISLBM_BF16DEV = 0, 1, 2, 3
+ISLBM_FP32, ISLBM_FP64, ISLBM_FP16DEV, ISLBM_BF16DEV, ISLBM_FP32SR = 0, 1, 2, 3, 4
 MESH_KINDS = {"uniform": 0, "erf": 1, "cosine": 2, "tanh": 3}
-STORAGE = {"fp32": ISLBM_FP32, "fp64": ISLBM_FP64, "fp16": ISLBM_FP16DEV, "bf16": ISLBM_BF16DEV}
+STORAGE = {"fp32": ISLBM_FP32, "fp64": ISLBM_FP64, "fp16": ISLBM_FP16DEV, "bf16": ISLBM_BF16DEV,
+           "fp32sr": ISLBM_FP32SR}
 
 EXPORTS = ("islbm_default_options", "islbm_query_bytes", "islbm_mesh_spacing", "islbm_create",
            "islbm_step", "islbm_fields", "islbm_fields_device", "islbm_nu_re",

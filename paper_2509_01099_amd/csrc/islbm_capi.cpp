@@ -109,7 +109,7 @@ static int pitch_for(int n0, int storage) {
 
 extern "C" int islbm_query_bytes(int lattice, const int n[3], int storage, size_t* f_bytes,
                                  size_t* g_bytes) {
-  if (!n || (lattice != 2 && lattice != 3) || storage < 0 || storage > 3) return ISLBM_EINVAL;
+  if (!n || (lattice != 2 && lattice != 3) || storage < 0 || storage > 4) return ISLBM_EINVAL;
   const int n2 = lattice == 3 ? n[2] : 1;
   if (n[0] < 3 || n[1] < 3 || n2 < (lattice == 3 ? 3 : 1)) return ISLBM_EINVAL;
   const size_t plane = (size_t)pitch_for(n[0], storage) * n[1] * n2;
@@ -207,7 +207,7 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
   islbm_options opt;
   if (opt_in) opt = *opt_in;
   else islbm_default_options(&opt);
-  if (opt.storage < 0 || opt.storage > 3) return fail(nullptr, ISLBM_EINVAL, "unknown storage");
+  if (opt.storage < 0 || opt.storage > 4) return fail(nullptr, ISLBM_EINVAL, "unknown storage");
   const int dim = lattice;
   int n[3] = {n_in[0], n_in[1], dim == 3 ? n_in[2] : 1};
   for (int a = 0; a < dim; ++a) {
@@ -307,7 +307,7 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
   c->no_graph = opt.no_graph;
 
   // ---- interpolation tables (Sec. 2.2) ------------------------------------
-  const bool dbl = opt.storage == ISLBM_FP64;
+  const bool dbl = opt.storage == ISLBM_FP64 || opt.storage == ISLBM_FP32SR;  // FP64 arithmetic
   std::vector<std::vector<double>> tab(3);
   bool onehot = true;
   for (int a = 0; a < 3; ++a) {

@@ -107,6 +107,27 @@ __device__ __forceinline__ S* at(S* p, unsigned off) {
   return reinterpret_cast<S*>(reinterpret_cast<char*>(p) + off * unsigned(sizeof(S)));
 }
 
+// FP32 storage with FP64 arithmetic: the same 4-byte deviations as FP32,
+// loaded into double, updated in double, and written back with stochastic
+// rounding from double (29 random bits below the kept float mantissa), so
+// that changes far below a float ulp are kept in expectation.
+struct f32s {
+  float x;
+};
+template <>
+struct Store<f32s> {
+  using R = double;
+  static constexpr bool kDither = true;
+  __device__ static double ld(const f32s* p) { return double(p->x); }
+  __device__ static void st(f32s* p, double v) { p->x = float(v); }
+  __device__ static void st_nt(f32s* p, double v) { __builtin_nontemporal_store(float(v), &p->x); }
+  __device__ static void st_dither(f32s* p, double v, unsigned bits) {
+    unsigned long long u = __double_as_longlong(v);
+    u = (u + ((unsigned long long)bits >> 3)) & ~0x1FFFFFFFull;  // exact in float across its normal range
+    p->x = float(__longlong_as_double(u));
+  }
+};
+
 // 32-bit integer hash "lowbias32" (C. Wellons, "Prospecting for hash
 // functions", 2018) of node and device-side step counter; the bits of
 // population i are the top bits of that hash times a distinct odd constant
@@ -511,7 +532,7 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   const unsigned dkey = dither_key<S>(a);
   // cache-resident class with FP32 arithmetic: scalar base + 32-bit offsets
   // (FP64 storage is always stepped with 64-bit addresses and plain stores)
-  constexpr bool OFF32 = !NTS && !std::is_same_v<S, double>;
+  constexpr bool OFF32 = !NTS && std::is_same_v<R, float>;
 
   const TileOrigin o = tile_origin<T>(a.n, a.tiles, a.nblocks);
   // 1. issue every global load of the tile (moving populations into staging
@@ -959,7 +980,8 @@ static hipError_t dispatch_step(const DevState& s, const void* fin, const void* 
 using March3 = March<32, 8, 32>;
 
 static bool use_march(const DevState& s) {
-  return s.dim == 3 && s.storage != 1 && s.uniform != 0 && s.collide != 0;
+  const bool fp32_arith = s.storage == 0 || s.storage == 2 || s.storage == 3;
+  return s.dim == 3 && fp32_arith && s.uniform != 0 && s.collide != 0;
 }
 
 static int march_grid(const DevState& s, int* tiles) {
@@ -998,6 +1020,7 @@ static hipError_t by_storage(int storage, int dim, Fn&& fn) {
     case 1: return fn(double{});
     case 2: return fn(__half{});
     case 3: return fn(__hip_bfloat16{});
+    case 4: return fn(f32s{});
     default: return hipErrorInvalidValue;
   }
 }
@@ -1006,6 +1029,7 @@ size_t storage_elem_bytes(int storage) {
   switch (storage) {
     case 0: return 4;
     case 1: return 8;
+    case 4: return 4;
     default: return 2;
   }
 }
@@ -1017,7 +1041,7 @@ static int blocks_for(const DevState& s) {
 }
 
 int step_blocks(const DevState& s) {
-  const bool dbl = s.storage == 1, lg = s.large != 0;
+  const bool dbl = s.storage == 1 || s.storage == 4, lg = s.large != 0;
   if (s.dim == 2) {
     if (dbl) return blocks_for<2, double, false>(s);
     return lg ? blocks_for<2, float, true>(s) : blocks_for<2, float, false>(s);
@@ -1034,7 +1058,7 @@ hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void
                        bool reduce, double* partials, hipStream_t st) {
   return by_storage(s.storage, s.dim, [&](auto tag) {
     using S = decltype(tag);
-    if constexpr (std::is_same_v<S, double>) {
+    if constexpr (std::is_same_v<typename Store<S>::R, double>) {
       return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
                         : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
     } else {

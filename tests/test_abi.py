@@ -55,8 +55,12 @@ def test_query_bytes():
     assert fb == 9 * 128 * 50 * 4 and gb == 5 * 128 * 50 * 4
     fb, gb = pkg.islbm_query_bytes(3, [256, 256, 256], pkg.ISLBM_FP16DEV)
     assert fb == 19 * 256 ** 3 * 2 and gb == 7 * 256 ** 3 * 2
+    fb, gb = pkg.islbm_query_bytes(2, [100, 50], pkg.ISLBM_FP32SR)   # FP32 storage
+    assert fb == 9 * 128 * 50 * 4 and gb == 5 * 128 * 50 * 4
     with pytest.raises(pkg.IslbmError):
         pkg.islbm_query_bytes(2, [2, 50], pkg.ISLBM_FP32)
+    with pytest.raises(pkg.IslbmError):
+        pkg.islbm_query_bytes(2, [100, 50], 5)                     # unknown storage
 
 
 def _create(n, sp, Ra=1e6, Pr=0.71, lattice=2, opt=None):

@@ -65,3 +65,28 @@ def test_reduced_storage_rest_state_exact(storage):
     assert np.array_equal(f, np.broadcast_to(w[:, None, None], f.shape))
     assert not np.any(g)
     cav.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fp32_storage_fp64_arithmetic_vs_oracle(dim):
+    """FP32 storage with FP64 arithmetic and stochastic rounding on store:
+    within the FP32 bars of the parity tests after 100 steps."""
+    oracle.set_threads(16)
+    meshes = [("tanh", 70, 1.5), ("tanh", 37, 1.5), ("tanh", 18, 1.5)][:dim]
+    cav, orc = make_pair(meshes, 1e6 if dim == 2 else 1e7, 0.71, storage="fp32sr")
+    _, w, _ = oracle.lattice(dim, 0)
+    f = random_populations(orc.shape, w, 0.05, seed=31)
+    g = random_scalar_populations(orc.shape, orc.qg, 0.5, seed=32)
+    cav.set_populations(f, g, post_collision=False)
+    orc.set_state(f, g)
+    cav.step(100)
+    orc.run(100)
+    fp, gp = cav.populations()
+    orc.collide()
+    ofp, ogp = orc.post()
+    ef, eg = rel_f(fp, ofp), rel_g(gp, ogp)
+    st, ost = cav.stats(), orc.stats()
+    enu = abs(st["nu_hot"] - ost["nu_hot"]) / max(abs(ost["nu_hot"]), 1.0)
+    print(f"fp32sr {dim}d: f {ef:.2e} g {eg:.2e} nu_hot {enu:.1e}", flush=True)
+    assert ef <= 1e-5 and eg <= 1e-5 and enu <= 1e-4
+    cav.close()
