@@ -926,7 +926,7 @@ struct TileFor<2, float, true> {
 };
 template <bool L>
 struct TileFor<2, double, L> {
-  using T = Tile<64, 8, 1, 2>;
+  using T = Tile<64, 4, 1, 1>;
 };
 template <bool L>
 struct TileFor<3, float, L> {
