@@ -527,8 +527,8 @@ def main() -> int:
                          "counter calibration (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path, so --gpus "
+              "must be 1", file=sys.stderr)
         return 2
     import torch
 

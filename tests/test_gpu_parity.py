@@ -68,7 +68,7 @@ def test_parity_2d_fp32_random(kind, seed):
     cav.close()
 
 
-def test_parity_2d_fp32_from_rest_cfg1_mesh():
+def test_parity_2d_fp32_from_rest_cosine64():
     """Start at rest (T = 0 inside, walls +-0.5) on the 64^2 cosine mesh with
     u_f = 0.1, Ra = 1e6 (the small 2-D workload), FP32, 100 steps."""
     cav, orc = make_pair([("cosine", 64, 0), ("cosine", 64, 0)], 1e6, 0.71, u_f=0.1,
@@ -100,7 +100,7 @@ def test_parity_2d_cosine256_ra1e8_subrun():
     cav.close()
 
 
-def test_parity_2d_fp64_cfg1_full_run():
+def test_parity_2d_fp64_cosine64_full_run():
     """The small 2-D workload in full: 64^2 cosine, Ra = 1e6, Pr = 0.71,
     u_f = 0.1, FP64, 20000 steps from rest."""
     oracle.set_threads(16)
@@ -108,7 +108,7 @@ def test_parity_2d_fp64_cfg1_full_run():
                          u_f=0.1, allow_unstable=1)
     cav.step(20000)
     orc.run(20000)
-    _compare(cav, orc, 1e-10, 1e-10, "2d fp64 cfg1 20k")
+    _compare(cav, orc, 1e-10, 1e-10, "2d fp64 cosine 64 20k")
     cav.close()
 
 
