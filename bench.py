@@ -204,6 +204,16 @@ def _wall_coords(sp):
     return (X[1:-1] - w0) / (0.5 * (X[-1] + X[-2]) - w0)
 
 
+def richardson(fc: float, fm: float, ff: float, r: float):
+    """Observed order p, extrapolated value and fine-mesh GCI in percent
+    (safety factor 1.25) from a coarse, medium and fine mesh refined by the
+    constant ratio r (Sec. 3; r = 2 for the 2-D table, r = 1.41 for the 3-D
+    table of Sec. 4)."""
+    p = math.log(abs((fc - fm) / (fm - ff))) / math.log(r)
+    rp = r ** p
+    return p, (rp * ff - fm) / (rp - 1), 1.25 * abs((ff - fm) / ff) / (rp - 1) * 100
+
+
 def converge(cav, max_steps: int, tol: float = 1e-9, interval: int = 2000,
              check: int = 50000, tag: str = ""):
     """Runs until the Sec. 3 steady-state measure over `interval` steps is
@@ -268,15 +278,110 @@ def convergence_study(Ra: float = 1e6, sizes=(257, 513, 1025), max_steps: int = 
            "runs": runs}
     if len(sizes) == 3:
         a, b, c3 = sizes
-        r = 2.0
         rich = {}
         for k in keys:
-            fc, fm, ff = vals[a][k], vals[b][k], vals[c3][k]
-            p = math.log(abs((fc - fm) / (fm - ff))) / math.log(r)
-            finf = (r ** p * ff - fm) / (r ** p - 1)
-            gci = 1.25 * abs((ff - fm) / ff) / (r ** p - 1) * 100
+            p, finf, gci = richardson(vals[a][k], vals[b][k], vals[c3][k], 2.0)
             rich[k] = {"p": p, "extrapolated": finf, "gci_fine_pct": gci}
         out["richardson"] = rich
+    return out
+
+
+# Sec. 4 table (3-D cavity, erf meshes a = 1.5): <Nu>, Nu_hot, Nu_cold, <Re>
+# of the present ISLBM per (Ra, N).
+TABLE_3D = {(1e5, 129): (4.3406, 4.3624, 4.3624, 39.4521),
+            (1e5, 181): (4.3363, 4.3520, 4.3520, 39.3768),
+            (1e5, 257): (4.3346, 4.3457, 4.3457, 39.3500),
+            (1e6, 181): (8.6601, 8.6931, 8.6931, 97.4828),
+            (1e6, 257): (8.6441, 8.6669, 8.6668, 97.0075),
+            (1e6, 361): (8.6379, 8.6540, 8.6540, 96.8464)}
+
+
+def converge_stats(cav, max_steps: int, tol: float = 1e-8, check: int = 20000, lag: int = 2,
+                   tag: str = ""):
+    """Steady criterion for storage with stochastic rounding: runs until
+    <Nu>, Nu_hot and Re (rms) change by less than `tol` (relative) over the
+    last `lag` checks of `check` steps.  The rounding noise is independent
+    from node to node and step to step, so it averages out of the domain
+    integrals but not out of the node-wise Sec. 3 measure, which is logged
+    alongside."""
+    keys = ("nu_vol", "nu_hot", "re_rms")
+    done, t0, hist = 0, time.perf_counter(), []
+    du = dT = float("inf")
+    while done < max_steps:
+        cav.step(check - 2000)
+        cav.steady_change()
+        cav.step(2000)
+        du, dT, _ = cav.steady_change()
+        done += check
+        st = cav.stats()
+        hist.append([st[k] for k in keys])
+        rel = (max(abs(a / b - 1) for a, b in zip(hist[-1], hist[-1 - lag]))
+               if len(hist) > lag else float("inf"))
+        _log(f"{tag} step {done} nu_vol {st['nu_vol']:.8f} change {rel:.1e} du {du:.1e} "
+             f"dT {dT:.1e} t={time.perf_counter() - t0:.0f}s")
+        if rel < tol:
+            break
+    return done, rel, du, dT, time.perf_counter() - t0
+
+
+def convergence_3d(Ra: float = 1e5, sizes=(129, 181, 257), storage: str = "fp32sr",
+                   max_steps=(600_000, 600_000, 600_000)) -> dict:
+    """Grid convergence of the steady 3-D cavity on the erf meshes of the
+    Sec. 4 table (a = 1.5): the coarsest mesh starts at rest, each finer mesh
+    from the previous mesh's steady fields (trilinear interpolation), each is
+    run until its integrals are steady; Richardson extrapolation and GCI with
+    the table's refinement ratio r = 1.41."""
+    import numpy as np
+    from scipy.interpolate import RegularGridInterpolator
+
+    import paper_2509_01099_amd as pkg
+    from paper_2509_01099_amd import warmstart as W
+
+    keys = ("nu_vol", "nu_hot", "nu_cold", "re_rms")
+    vals, runs, prev = {}, [], None
+    for n, cap in zip(sizes, max_steps):
+        sp = W.mesh_spacing("erf", n, 1.5)
+        cav = pkg.Cavity([sp, sp, sp], Ra, PR, storage=storage)
+        c = _wall_coords(sp)
+        if prev is not None:
+            pc, pf = prev
+            zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
+            pts = np.column_stack([zz.ravel(), yy.ravel(), xx.ravel()])
+            del zz, yy, xx
+            init = {}
+            for k in ("ux", "uy", "uz", "T"):
+                init[k] = RegularGridInterpolator((pc, pc, pc), pf[k], bounds_error=False,
+                                                  fill_value=None)(pts).reshape(n, n, n)
+                _log(f"{n}^3: interpolated {k}")
+            del pts
+            cav.init_fields(init["ux"], init["uy"], init["uz"], init["T"])
+            del init
+        steps, rel, du, dT, secs = converge_stats(cav, cap, tag=f"{n}^3")
+        st = cav.stats()
+        f = cav.fields()
+        prev = (c, {k: f[k] for k in ("ux", "uy", "uz", "T")})
+        del f
+        vals[n] = {k: st[k] for k in keys}
+        row = {"n": n, "steps": steps, "integral_change": rel, "du": du, "dT": dT,
+               "seconds": round(secs, 1), "mlups": round(n ** 3 * steps / secs / 1e6, 1),
+               **vals[n]}
+        ref = TABLE_3D.get((Ra, n))
+        if ref:
+            row["paper"] = dict(zip(("nu_vol", "nu_hot", "nu_cold", "re"), ref))
+        runs.append(row)
+        _log(f"{n}^3: {row}")
+        cav.close()
+    out = {"workload": f"3-D cavity Ra={Ra:g} Pr=0.71, erf meshes a=1.5, {storage}, coarsest "
+                       "from rest, each finer mesh from the previous steady fields",
+           "runs": runs}
+    if len(sizes) == 3:
+        out["richardson"] = {}
+        for k in keys:
+            try:
+                p, finf, gci = richardson(*(vals[n][k] for n in sizes), 1.41)
+            except (ValueError, ZeroDivisionError):     # not monotone in N, or equal
+                p = finf = gci = None
+            out["richardson"][k] = {"p": p, "extrapolated": finf, "gci_fine_pct": gci}
     return out
 
 
@@ -309,6 +414,56 @@ def validation_3d(n: int = 129, Ra: float = 1e5, max_steps: int = 1_200_000,
 
 def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+# The paper's two performance cases (erf meshes, a = 2.1, Pr = 0.71, Ma = 0.1)
+# with its wall-clock time per free-fall time on one A100 in FP64 (Sec. 3 and
+# Sec. 4); steps timed per case.
+PAPER_WCTPDT = ((2, 8193, 1e8, 1.5722e4, 400), (3, 400, 1e7, 1.456e3, 200))
+
+
+def wctpdt_study(storages=("fp64", "fp32sr", "fp32", "fp16")) -> dict:
+    """Wall-clock time per dimensionless time (Eq. 27) on the paper's two
+    performance cases, with the uniform mesh of the same node count beside
+    each.  One free-fall time t_f = H/u_f takes H_lu/u_f steps, so WCTpDT is
+    the measured time per step (device events over the timed launches) times
+    H_lu/u_f.  The cavities start at rest; the step's cost does not depend on
+    the flow."""
+    import paper_2509_01099_amd as pkg
+
+    uf = 0.1 / 3 ** 0.5
+    rows = []
+    for dim, n, Ra, paper_s, steps in PAPER_WCTPDT:
+        for st in storages:
+            pair = {}
+            for kind in ("erf", "uniform"):
+                sp = pkg.islbm_mesh_spacing(kind, n, 2.1)
+                sp = sp / sp[0]
+                cav = pkg.Cavity([sp] * dim, Ra, PR, storage=st, u_f=uf)
+                H = cav.info["H_lu"]
+                _, dev = time_run(cav, steps, 20)
+                bad = cav.stats(allow_nonfinite=True)["nonfinite"]
+                cav.close()
+                per = dev / steps
+                nodes = n ** dim
+                row = {"dim": dim, "n": n, "Ra": Ra, "mesh": kind, "storage": st,
+                       "H_lu": round(H, 3), "steps_per_tf": round(H / uf, 1),
+                       "ms_per_step": round(per * 1e3, 4),
+                       "mlups": round(nodes / per / 1e6, 1),
+                       "wctpdt_s": round(per * H / uf, 2), "nonfinite": bad}
+                if kind == "erf":
+                    row["paper_a100_fp64_s"] = paper_s
+                    row["paper_over_ours"] = round(paper_s / row["wctpdt_s"], 2)
+                pair[kind] = row
+                rows.append(row)
+                _log(f"{dim}-D {n}^{dim} {kind} {st}: {row['mlups']} MLUPS, "
+                     f"WCTpDT {row['wctpdt_s']} s")
+            pair["erf"]["mlups_over_uniform"] = round(pair["erf"]["mlups"] /
+                                                      pair["uniform"]["mlups"], 3)
+            pair["erf"]["wctpdt_over_uniform"] = round(pair["erf"]["wctpdt_s"] /
+                                                       pair["uniform"]["wctpdt_s"], 3)
+    return {"study": "WCTpDT on the paper's performance cases (erf a=2.1, Ma=0.1, "
+                     "from rest; one MI355X)", "rows": rows}
 
 
 def _ws_setup(n: int):
@@ -517,6 +672,15 @@ def main() -> int:
                     help="grid-convergence study instead of the headline line: 2-D cavity at "
                          "this Ra on erf meshes 257/513/1025 (1e6) or 513/1025/2049, FP64, "
                          "run to the steady criterion; observed order and extrapolation")
+    ap.add_argument("--wctpdt", action="store_true",
+                    help="wall-clock time per free-fall time on the paper's performance cases "
+                         "(2-D 8193^2 Ra 1e8, 3-D 400^3 Ra 1e7, erf a=2.1) and their uniform "
+                         "meshes, FP64 / FP32SR / FP32 / FP16")
+    ap.add_argument("--convergence3d", type=float, default=0.0, metavar="RA",
+                    help="3-D grid-convergence study at this Ra on the erf meshes of the paper's "
+                         "3-D table (1e5: 129/181/257), FP32 storage with FP64 arithmetic")
+    ap.add_argument("--c3-sizes", default="",
+                    help="comma-separated mesh sizes of --convergence3d (default: the table's)")
     ap.add_argument("--validation3d", action="store_true",
                     help="steady 3-D cavity (129^3 erf, Ra 1e5, FP64) against the paper's table")
     ap.add_argument("--profile-mesh", choices=["2d", "3d", "3d-uniform"], default="2d",
@@ -539,6 +703,15 @@ def main() -> int:
     n = (N_CFG, N_CFG)
     nodes = N_CFG * N_CFG
 
+    if args.convergence3d:
+        sizes = tuple(int(v) for v in args.c3_sizes.split(",")) if args.c3_sizes else (
+            (129, 181, 257) if args.convergence3d < 5e5 else (181, 257, 361))
+        caps = (600_000, 500_000, 450_000)[:len(sizes)]
+        print(json.dumps(convergence_3d(args.convergence3d, sizes, max_steps=caps)))
+        return 0
+    if args.wctpdt:
+        print(json.dumps(wctpdt_study()))
+        return 0
     if args.validation3d:
         print(json.dumps(validation_3d()))
         return 0
