@@ -419,7 +419,8 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
   }
   islbm_query_bytes(lattice, n, opt.storage, &c->fbytes, &c->gbytes);
   // read + write buffers of one step against the 256 MB last-level cache
-  s.large = 2 * (c->fbytes + c->gbytes) > (size_t(192) << 20) ? 1 : 0;
+  const size_t ws = 2 * (c->fbytes + c->gbytes);
+  s.large = ws > (size_t(1) << 30) ? 2 : (ws > (size_t(192) << 20) ? 1 : 0);
   const bool given = opt.buffers[0] || opt.buffers[1] || opt.buffers[2] || opt.buffers[3];
   if (given) {
     for (int i = 0; i < 4; ++i)

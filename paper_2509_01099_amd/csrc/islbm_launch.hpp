@@ -21,7 +21,8 @@ struct DevState {
   double inv_uf, inv_dT;
   int collide;     // 0 => collision is the identity
   int uniform;     // 1 => every interpolation weight is one-hot (uniform mesh)
-  int large;       // 1 => the two population buffers exceed the last-level cache
+  int large;       // read + write population buffers: 0 fit the last-level cache,
+                   // 1 exceed it, 2 exceed 1 GB
   // per-axis interpolation weights: axis a holds [2][n[a]][4] of float or
   // double (first block: lattice direction +1, second: -1); wall links are 0
   const void* wtab[3];

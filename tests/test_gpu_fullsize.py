@@ -36,7 +36,7 @@ def sample_nodes(shape, rng, count=4000):
 
 # one step of 2-byte storage: the stored deviation of a value is off by at most
 # one unit in the last place after stochastic rounding (2^-10 of |g| in FP16)
-TOL = {"fp32": (1e-5, 1e-5), "fp16": (1e-4, 2e-3), "fp32sr": (1e-5, 1e-5)}
+TOL = {"fp32": (1e-5, 1e-5), "fp16": (1e-4, 2e-3), "fp32sr": (1e-5, 1e-5), "fp64": (1e-10, 1e-10)}
 
 
 @pytest.mark.parametrize("dim,kind,n,Ra,storage", [
@@ -44,6 +44,8 @@ TOL = {"fp32": (1e-5, 1e-5), "fp16": (1e-4, 2e-3), "fp32sr": (1e-5, 1e-5)}
     (2, "erf", (2050, 1100), 1e8, "fp32"),         # beyond the last-level cache: tall tiles
     (2, "erf", (4096, 2048), 1e8, "fp16"),         # 2-byte storage, large class
     (2, "cosine", (1024, 1024), 1e8, "fp32sr"),    # FP32 storage, FP64 arithmetic
+    (2, "erf", (4096, 2048), 1e8, "fp64"),         # FP64 beyond 1 GB: streaming stores
+    (3, "tanh", (256, 256, 256), 1e7, "fp32sr"),   # the same for FP64 arithmetic in 3-D
     (3, "tanh", (256, 256, 256), 1e7, "fp32"),     # the 3-D workload
     (3, "uniform", (256, 256, 256), 1e7, "fp32"),  # uniform 3-D: z-marching kernel
 ])
