@@ -3,7 +3,7 @@
 Workload (the metric's headline configuration): 2-D side-heated cavity,
 Ra = 1e8, Pr = 0.71, 1024 x 1024 cosine-stretched mesh (x_j = (1 - cos(pi
 j/(N+1)))/2 on both axes), D2Q9 flow + D2Q5 temperature populations, FP32
-structure-of-arrays storage, start at rest, walls +-0.5.  One "step" is one
+storage in population rows, start at rest, walls +-0.5.  One "step" is one
 fused launch over the whole mesh.  Printed next to it: the same size on a
 uniform mesh (plain-shift kernel), HBM roofline of the dominant kernel, and
 the FP64 CPU oracle timed on the host cores over a bounded sample.
@@ -806,7 +806,7 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic (cavity started at rest; no external data)",
         "config": {"workload": "2-D side-heated cavity, Ra=1e8, Pr=0.71, 1024x1024 "
-                               "cosine-stretched mesh, D2Q9+D2Q5 MRT, FP32 SoA populations",
+                               "cosine-stretched mesh, D2Q9+D2Q5 MRT, FP32 populations in [z][y][pop][x] rows",
                    "u_f": uf, "H_lu": H, "nodes": nodes,
                    "wctpdt_s": round(wall / args.steps * H / uf, 3),
                    "nonfinite_nodes": st["nonfinite"]},

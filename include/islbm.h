@@ -34,8 +34,10 @@
  *             14 (-1,0,1); 15 (0,1,1); 16 (0,-1,-1); 17 (0,1,-1); 18 (0,-1,1)
  *      D3Q7 : 0; 1 +x; 2 -x; 3 +y; 4 -y; 5 +z; 6 -z
  *  - The state kept between calls is the post-collision population set
- *    f+(x,t), g+(x,t) (Sec. 2.1, collision step), held on the device in
- *    structure-of-arrays form as deviations f - w_i (flow) and g (thermal).
+ *    f+(x,t), g+(x,t) (Sec. 2.1, collision step), held on the device as
+ *    deviations f - w_i (flow) and g (thermal), in x-rows: for every (z, y)
+ *    row of the mesh the rows of all populations of a set lie one after
+ *    another ([z][y][pop][x], padded row pitch).
  *  - Every call returns 0 on success or a negative islbm_status.  Out
  *    parameters are untouched on error.  Calls on one context are not
  *    thread-safe; distinct contexts are independent.  Work is enqueued on the

@@ -286,6 +286,10 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
   for (int a = 0; a < 3; ++a) s.n[a] = n[a];
   s.pitch = pitch_for(n[0], opt.storage);
   s.plane = (long long)s.pitch * n[1] * n[2];
+  // populations interleaved by rows: [z][y][pop][x]
+  s.ps = s.pitch;
+  s.rsf = (long long)c->qf * s.pitch;
+  s.rsg = (long long)c->qg * s.pitch;
   s.s_nu = snu;
   s.s_e = opt.s_e > 0 ? opt.s_e : snu;
   s.s_eps = opt.s_eps > 0 ? opt.s_eps : snu;
@@ -673,7 +677,7 @@ extern "C" int islbm_get_populations(islbm_ctx* ctx, double* f, double* g) {
     const int q = set == 0 ? ctx->qf : ctx->qg;
     const char* base = static_cast<const char*>(set == 0 ? fbuf(ctx, ctx->cur) : gbuf(ctx, ctx->cur));
     for (int p = 0; p < q; ++p) {
-      const void* plane = base + (size_t)p * ctx->s.plane * elem_bytes(ctx->storage);
+      const void* plane = base + (size_t)p * ctx->s.ps * elem_bytes(ctx->storage);
       hipError_t e = islbm::launch_convert_out(ctx->s, plane, ctx->staging, p, set == 0, ctx->stream);
       if (e != hipSuccess) return hipfail(ctx, e, "convert kernel");
       HIPCHECK(ctx, hipMemcpyAsync(host + (size_t)p * ctx->nn, ctx->staging, bytes, hipMemcpyDeviceToHost,
@@ -698,7 +702,7 @@ extern "C" int islbm_set_populations(islbm_ctx* ctx, const double* f, const doub
     for (int p = 0; p < q; ++p) {
       HIPCHECK(ctx, hipMemcpyAsync(ctx->staging, host + (size_t)p * ctx->nn, bytes, hipMemcpyHostToDevice,
                                    ctx->stream));
-      void* plane = base + (size_t)p * ctx->s.plane * elem_bytes(ctx->storage);
+      void* plane = base + (size_t)p * ctx->s.ps * elem_bytes(ctx->storage);
       hipError_t e = islbm::launch_convert_in(ctx->s, ctx->staging, plane, p, set == 0, ctx->stream);
       if (e != hipSuccess) return hipfail(ctx, e, "convert kernel");
       HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));

@@ -14,7 +14,10 @@ struct DevState {
   int storage;     // islbm_storage
   int n[3];        // fluid nodes per axis (n[2] = 1 in 2-D)
   int pitch;       // row pitch in elements (>= n[0])
-  long long plane; // elements per population plane
+  long long plane; // elements per population (pitch x n[1] x n[2])
+  long long ps;    // elements between the rows of two populations of a (z, y) row
+  long long rsf;   // elements between consecutive rows of one f population
+  long long rsg;   // elements between consecutive rows of one g population
   // relaxation and physics, lattice units
   double s_e, s_eps, s_q, s_nu, s_pi, s_m, q_j, q_e, q_nu, aT;
   double gbeta, T0, omega, Thot, Tcold;
