@@ -926,9 +926,10 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
 
 // Tile shapes per lattice, arithmetic width and working-set class (TX x TY x
 // TZ nodes, NR nodes per thread).  "Large" means the two population buffers
-// do not fit the 256 MB last-level cache: those launches use taller tiles
-// (fewer halo re-reads) and streaming stores; cache-resident meshes use
-// short tiles (more workgroups per CU) and ordinary stores.
+// do not fit the 256 MB last-level cache: those launches use larger 2-D
+// tiles with two rows per thread (fewer halo re-reads) and streaming stores;
+// cache-resident meshes use small tiles (more workgroups per CU) and
+// ordinary stores.  Shapes are from sweeps on MI355X.
 template <int D, typename R, bool LARGE>
 struct TileFor;
 template <>
@@ -937,7 +938,7 @@ struct TileFor<2, float, false> {
 };
 template <>
 struct TileFor<2, float, true> {
-  using T = Tile<64, 8, 1, 2>;
+  using T = Tile<128, 4, 1, 2>;
 };
 template <bool L>
 struct TileFor<2, double, L> {
@@ -961,7 +962,7 @@ static int grid_of(const DevState& s, int* tiles) {
 }
 
 // 2-byte storage in 2-D keeps the short 64 x 4 tiles also for large meshes
-// (measured 13 % faster there than the taller FP32 tiles).
+// (measured 13 % faster there than 64 x 8 tiles with two rows per thread).
 template <int D, typename S, bool LARGE>
 struct TileSel {
   using T = typename TileFor<D, typename Store<S>::R, LARGE>::T;

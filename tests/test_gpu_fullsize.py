@@ -41,7 +41,7 @@ TOL = {"fp32": (1e-5, 1e-5), "fp16": (1e-4, 2e-3), "fp32sr": (1e-5, 1e-5), "fp64
 
 @pytest.mark.parametrize("dim,kind,n,Ra,storage", [
     (2, "cosine", (1024, 1024), 1e8, "fp32"),      # the benchmark workload
-    (2, "erf", (2050, 1100), 1e8, "fp32"),         # beyond the last-level cache: tall tiles
+    (2, "erf", (2050, 1100), 1e8, "fp32"),         # beyond the last-level cache: large tiles
     (2, "erf", (4096, 2048), 1e8, "fp16"),         # 2-byte storage, large class
     (2, "cosine", (1024, 1024), 1e8, "fp32sr"),    # FP32 storage, FP64 arithmetic
     (2, "erf", (4096, 2048), 1e8, "fp64"),         # FP64 beyond 1 GB: streaming stores
