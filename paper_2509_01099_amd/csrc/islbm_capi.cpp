@@ -677,8 +677,8 @@ extern "C" int islbm_get_populations(islbm_ctx* ctx, double* f, double* g) {
     const int q = set == 0 ? ctx->qf : ctx->qg;
     const char* base = static_cast<const char*>(set == 0 ? fbuf(ctx, ctx->cur) : gbuf(ctx, ctx->cur));
     for (int p = 0; p < q; ++p) {
-      const void* plane = base + (size_t)p * ctx->s.ps * elem_bytes(ctx->storage);
-      hipError_t e = islbm::launch_convert_out(ctx->s, plane, ctx->staging, p, set == 0, ctx->stream);
+      const void* row0 = base + (size_t)p * ctx->s.ps * elem_bytes(ctx->storage);
+      hipError_t e = islbm::launch_convert_out(ctx->s, row0, ctx->staging, p, set == 0, ctx->stream);
       if (e != hipSuccess) return hipfail(ctx, e, "convert kernel");
       HIPCHECK(ctx, hipMemcpyAsync(host + (size_t)p * ctx->nn, ctx->staging, bytes, hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -702,8 +702,8 @@ extern "C" int islbm_set_populations(islbm_ctx* ctx, const double* f, const doub
     for (int p = 0; p < q; ++p) {
       HIPCHECK(ctx, hipMemcpyAsync(ctx->staging, host + (size_t)p * ctx->nn, bytes, hipMemcpyHostToDevice,
                                    ctx->stream));
-      void* plane = base + (size_t)p * ctx->s.ps * elem_bytes(ctx->storage);
-      hipError_t e = islbm::launch_convert_in(ctx->s, ctx->staging, plane, p, set == 0, ctx->stream);
+      void* row0 = base + (size_t)p * ctx->s.ps * elem_bytes(ctx->storage);
+      hipError_t e = islbm::launch_convert_in(ctx->s, ctx->staging, row0, p, set == 0, ctx->stream);
       if (e != hipSuccess) return hipfail(ctx, e, "convert kernel");
       HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
     }

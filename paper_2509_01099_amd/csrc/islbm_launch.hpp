@@ -45,6 +45,10 @@ int step_blocks(const DevState& s);
 hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void* fout,
                        void* gout, bool reduce, double* partials, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// One population between a dense FP64 node array (x fastest) and its rows in
+// a population buffer: dst / src point at the population's first row (the
+// buffer plus pop * ps elements); flow = 1 for f (weights subtracted / added
+// back), 0 for g.
 hipError_t launch_convert_in(const DevState& s, const double* src, void* dst, int pop, int flow,
                              hipStream_t st);
 hipError_t launch_convert_out(const DevState& s, const void* src, double* dst, int pop, int flow,
