@@ -1,0 +1,66 @@
+"""Host logic of the studies in bench.py, run without a GPU: a stand-in
+cavity whose integrals follow a known power law in the mesh spacing checks
+that the 3-D convergence study interpolates each mesh's fields onto the next
+one, stops on its integral criterion and returns the Richardson order of the
+law."""
+import numpy as np
+
+import bench
+import paper_2509_01099_amd as pkg
+
+
+class _Cavity:
+    P = 2.5
+
+    def __init__(self, sp, Ra, Pr, storage):
+        self.n = len(sp[0]) - 1
+        self.steps = 0
+        self.inits = None
+
+    def init_fields(self, ux, uy, uz, T):
+        self.inits = (ux, uy, uz, T)
+
+    def step(self, k):
+        self.steps += k
+
+    def steady_change(self):
+        return 1e-9, 1e-9, self.steps
+
+    def stats(self):
+        h = 1.0 / self.n
+        decay = np.exp(-self.steps / 20000.0)          # reaches a steady value
+        v = {"nu_vol": 4.3 + 2.0 * h ** self.P, "nu_hot": 4.3 + 3.0 * h ** self.P,
+             "nu_cold": 4.3 + 3.0 * h ** self.P, "re_rms": 39.0 - 50.0 * h ** self.P}
+        return {k: x * (1 + 1e-3 * decay) for k, x in v.items()}
+
+    def fields(self):
+        c = np.linspace(0.0, 1.0, self.n)
+        T = np.broadcast_to(0.5 - c[None, None, :], (self.n,) * 3).copy()
+        return {"ux": 0 * T, "uy": 0 * T, "uz": 0 * T, "T": T}
+
+    def close(self):
+        pass
+
+
+def test_convergence_3d_host_logic(monkeypatch):
+    made = []
+
+    def factory(*a, **k):
+        made.append(_Cavity(*a, **k))
+        return made[-1]
+
+    monkeypatch.setattr(pkg, "Cavity", factory)
+    sizes = (9, 13, 19)
+    out = bench.convergence_3d(1e5, sizes, max_steps=(10 ** 6,) * 3)
+    assert made[0].inits is None
+    for cav, n in zip(made[1:], sizes[1:]):
+        assert all(a.shape == (n, n, n) for a in cav.inits)
+        # T is linear in x: the interpolated field is the same linear profile
+        assert abs(cav.inits[3][0, 0, 0] - cav.inits[3][0, 0, -1] - 1.0) < 0.2
+    for run in out["runs"]:
+        assert run["integral_change"] < 1e-8
+    assert set(out["richardson"]) == {"nu_vol", "nu_hot", "nu_cold", "re_rms"}
+    # a power law sampled at ratios 13/9 and 19/13 (not exactly 1.41) gives
+    # an order near the law's when read with r = 1.41
+    p = out["richardson"]["nu_vol"]["p"]
+    assert abs(p - _Cavity.P) < 0.3, p
