@@ -108,10 +108,16 @@ def cpu_baseline(seconds_target: float = 15.0):
         el = time.perf_counter() - t0
     mlups = N_CFG * N_CFG * steps / el / 1e6
     del np
+    cpu = "host CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.get_threads(),
             "kind": "oracle",
             "sample": f"{steps} steps of the 1024^2 cosine 2-D cavity (Ra 1e8, FP64) in "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s on {oracle.get_threads()} threads of {cpu}"}
 
 
 def precision_study(steps: int, n: int = 384, steady_steps: int = 1_600_000) -> dict:
