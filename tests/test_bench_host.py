@@ -64,3 +64,36 @@ def test_convergence_3d_host_logic(monkeypatch):
     # an order near the law's when read with r = 1.41
     p = out["richardson"]["nu_vol"]["p"]
     assert abs(p - _Cavity.P) < 0.3, p
+
+
+def test_wctpdt_rows_scale_with_free_fall_time(monkeypatch):
+    """WCTpDT = time per step x H_lu / u_f; the erf row carries the paper's
+    figure and the ratios to the uniform mesh of the same node count."""
+
+    class Cav:
+        def __init__(self, sp, Ra, Pr, storage, u_f):
+            self.H = float(np.sum(sp[0]) - 0.5 * sp[0][0] - 0.5 * sp[0][-1])
+            self.uf = u_f
+
+        @property
+        def info(self):
+            return {"H_lu": self.H}
+
+        def stats(self, allow_nonfinite=False):
+            return {"nonfinite": 0}
+
+        def close(self):
+            pass
+
+    monkeypatch.setattr(pkg, "Cavity", Cav)
+    monkeypatch.setattr(bench, "PAPER_WCTPDT", ((2, 65, 1e8, 100.0, 10),))
+    monkeypatch.setattr(bench, "time_run", lambda cav, steps, warm: (0.0, steps * 1e-3))
+    out = bench.wctpdt_study(storages=("fp64",))
+    erf, uni = out["rows"]
+    uf = 0.1 / 3 ** 0.5
+    for r in (erf, uni):
+        assert abs(r["wctpdt_s"] - 1e-3 * r["H_lu"] / uf) < 0.01
+        assert abs(r["mlups"] - 65 * 65 / 1e-3 / 1e6) < 0.1
+    assert abs(uni["H_lu"] - 65) < 1e-9 and erf["H_lu"] > 65
+    assert abs(erf["paper_over_ours"] - 100.0 / erf["wctpdt_s"]) < 0.01
+    assert abs(erf["wctpdt_over_uniform"] / (erf["H_lu"] / 65) - 1) < 1e-2   # rounded rows
