@@ -388,6 +388,27 @@ def test_centro_symmetry():
     assert np.abs(fl["T"]).max() > 1e-3 and np.abs(fl["uy"]).max() > 1e-7
 
 
+def test_three_d_mirror_and_centro_symmetry():
+    """3-D cavity (gravity along y, isothermal x walls): the developing flow is
+    mirror-symmetric about the mid-z plane (u, v, T even, w odd) and
+    centro-symmetric about the centre, while w itself is not zero.  An error
+    in a z component of a D3Q19/D3Q7 velocity or in an opposite-population
+    pairing breaks one of the two."""
+    x = oracle.mesh("tanh", 10, 1.5)
+    o = oracle.Oracle([x, x, x], 1e5, 0.71, uf=0.1)
+    o.run(150)
+    fl = o.fields()
+    ux, uy, uz, T = fl["ux"], fl["uy"], fl["uz"], fl["T"]      # (nz, ny, nx)
+    tol = 1e-10
+    assert np.abs(ux - ux[::-1]).max() <= tol * np.abs(ux).max()
+    assert np.abs(uy - uy[::-1]).max() <= tol * np.abs(uy).max()
+    assert np.abs(uz + uz[::-1]).max() <= tol * np.abs(uz).max()
+    assert np.abs(T - T[::-1]).max() <= tol * np.abs(T).max()
+    for a in (ux, uy, uz, T):
+        assert np.abs(a + a[::-1, ::-1, ::-1]).max() <= tol * np.abs(a).max()
+    assert np.abs(uz).max() > 1e-2 * np.abs(uy).max()
+
+
 # --------------------------------------------------------- exact solutions ---
 
 def _decay_rate(series, t):
