@@ -498,6 +498,26 @@ def test_conduction_limit(kind):
     assert np.abs(T - lin[None, :]).max() < 1e-9
 
 
+def test_conduction_limit_3d():
+    """Property (d1) in 3-D (tanh mesh, 10^3): linear temperature between the
+    isothermal x walls and Nu_hot = Nu_cold = <Nu> = 1."""
+    n = 10
+    x = oracle.mesh("tanh", n, 1.5)
+    Ra, Pr = 1e-6, 0.71
+    H = 1.0 / x[1] - 1.0
+    uf = 0.08 * np.sqrt(Ra * Pr) / H                 # alpha_lu = 0.08
+    o = oracle.Oracle([x, x, x], Ra, Pr, uf=uf)
+    assert abs(o.params["alpha"] - 0.08) < 1e-12
+    o.run(9000)
+    s = o.stats()
+    for k in ("nu_hot", "nu_cold", "nu_vol"):
+        assert abs(s[k] - 1.0) < 1e-11, (k, s[k])
+    T = o.fields()["T"]
+    wall0, wall1 = 0.5 * (x[0] + x[1]), 0.5 * (x[-2] + x[-1])
+    lin = 0.5 - (x[1:-1] - wall0) / (wall1 - wall0)
+    assert np.abs(T - lin[None, None, :]).max() < 1e-9
+
+
 def test_observed_order_of_the_developing_flow():
     """Property (d2), on the transient: at a fixed time in free-fall units
     (t u_f / H = 2, Ra = 1e5, erf meshes a = 1.5 with N = 33, 65, 129; the
