@@ -418,6 +418,40 @@ def validation_3d(n: int = 129, Ra: float = 1e5, max_steps: int = 1_200_000,
     return out
 
 
+def throughput_table() -> dict:
+    """MLUPS and algorithmic TB/s of every storage type on the 2-D benchmark
+    mesh (1024^2 cosine, Ra 1e8), beyond the cache (4096^2) and on the 3-D
+    meshes (256^3 and 384^3 tanh, Ra 1e7), with the uniform meshes of the same
+    sizes; device events over the timed launches, from rest."""
+    cases = [("cosine", (1024, 1024), st, k) for st, k in
+             (("fp32", 3000), ("fp64", 1500), ("fp32sr", 1500), ("fp16", 3000), ("bf16", 3000))]
+    cases.append(("uniform", (1024, 1024), "fp32", 3000))
+    cases += [("cosine", (4096, 4096), st, k) for st, k in
+              (("fp32", 300), ("fp64", 150), ("fp32sr", 300), ("fp16", 300), ("bf16", 300))]
+    cases.append(("uniform", (4096, 4096), "fp32", 300))
+    cases += [("tanh", (256, 256, 256), st, k) for st, k in
+              (("fp32", 300), ("fp64", 150), ("fp32sr", 200), ("fp16", 300))]
+    cases.append(("uniform", (256, 256, 256), "fp32", 300))
+    cases += [("tanh", (384, 384, 384), st, k) for st, k in
+              (("fp32", 100), ("fp64", 50), ("fp32sr", 60), ("fp16", 100), ("bf16", 100))]
+    rows = []
+    for kind, shape, st, steps in cases:
+        three = len(shape) == 3
+        cav, _, _ = make_cavity(kind, shape, storage=st, Ra=1e7 if three else RA,
+                                **({"u_f": 0.0} if three else {}))
+        _, dev = time_run(cav, steps, 10)
+        bad = cav.stats(allow_nonfinite=True)["nonfinite"]
+        cav.close()
+        nodes = math.prod(shape)
+        mlups = nodes * steps / dev / 1e6
+        rows.append({"mesh": kind, "shape": list(shape), "storage": st, "steps": steps,
+                     "mlups": round(mlups, 1),
+                     "algorithmic_TBs": round(mlups * 1e6 * BYTES_PER_LU[len(shape)][st] / 1e12, 3),
+                     "nonfinite": bad})
+        _log(f"{kind} {shape} {st}: {rows[-1]['mlups']} MLUPS")
+    return {"study": "throughput of every storage type (one MI355X)", "rows": rows}
+
+
 def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -678,6 +712,8 @@ def main() -> int:
                     help="grid-convergence study instead of the headline line: 2-D cavity at "
                          "this Ra on erf meshes 257/513/1025 (1e6) or 513/1025/2049, FP64, "
                          "run to the steady criterion; observed order and extrapolation")
+    ap.add_argument("--throughput", action="store_true",
+                    help="MLUPS of every storage type on the 2-D and 3-D benchmark meshes")
     ap.add_argument("--wctpdt", action="store_true",
                     help="wall-clock time per free-fall time on the paper's performance cases "
                          "(2-D 8193^2 Ra 1e8, 3-D 400^3 Ra 1e7, erf a=2.1) and their uniform "
@@ -714,6 +750,9 @@ def main() -> int:
             (129, 181, 257) if args.convergence3d < 5e5 else (181, 257, 361))
         caps = (600_000, 500_000, 450_000)[:len(sizes)]
         print(json.dumps(convergence_3d(args.convergence3d, sizes, max_steps=caps)))
+        return 0
+    if args.throughput:
+        print(json.dumps(throughput_table()))
         return 0
     if args.wctpdt:
         print(json.dumps(wctpdt_study()))
