@@ -701,11 +701,12 @@ def main() -> int:
     ap.add_argument("--ws-n", type=int, default=257, help="warm-start mesh size (erf, a=1.5)")
     ap.add_argument("--ws-phase", choices=["all", "cold", "eval"], default="all",
                     help="'cold' runs the cold solves of one batch of Ra indices and writes "
-                         "gpurun_out/ws<n>_cold_<batch>.npz; 'eval' reads those files from "
+                         "<ws-dir>/ws<n>_cold_<batch>.npz; 'eval' reads those files from "
                          "--ws-dir and does training and the warm/cold comparison")
     ap.add_argument("--ws-batch", type=int, default=0)
     ap.add_argument("--ws-batch-size", type=int, default=8)
-    ap.add_argument("--ws-dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--ws-dir", default=os.path.join(ROOT, "ws_out"),
+                    help="directory of the cold-solve files of --ws-phase cold / eval")
     ap.add_argument("--ws-warm-steps", type=int, default=0,
                     help="steps of the warm runs (default: as many as the cold solves)")
     ap.add_argument("--convergence", type=float, default=0.0, metavar="RA",
@@ -768,7 +769,7 @@ def main() -> int:
         if args.ws_phase == "cold":
             ids = list(range(40))[args.ws_batch * args.ws_batch_size:
                                   (args.ws_batch + 1) * args.ws_batch_size]
-            out_dir = os.path.join(ROOT, "gpurun_out")
+            out_dir = args.ws_dir
             os.makedirs(out_dir, exist_ok=True)
             path = os.path.join(out_dir, f"ws{args.ws_n}_cold_{args.ws_batch}.npz")
             hist, _ = warmstart_cold(args.warmstart, args.ws_n, ids, out_path=path)
