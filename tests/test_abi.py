@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "islbm.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(islbm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(islbm_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -26,6 +26,17 @@ def test_library_exports_every_declared_symbol():
     for s in syms:
         assert hasattr(lib, s), s
     assert set(syms) == set(pkg.EXPORTS)
+
+
+def test_library_exports_every_mlp_symbol():
+    """The warm-start network kernels declared in include/islbm_mlp.h."""
+    text = open(os.path.join(ROOT, "include", "islbm_mlp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    syms = sorted(set(re.findall(r"\b(islbm_[a-z0-9_]+)\s*\(", text)))
+    assert len(syms) >= 8
+    lib = pkg.load()
+    for s in syms:
+        assert hasattr(lib, s), s
 
 
 def test_options_struct_matches_header():
