@@ -5,10 +5,15 @@ Ra = 1e8, Pr = 0.71, 1024 x 1024 cosine-stretched mesh (x_j = (1 - cos(pi
 j/(N+1)))/2 on both axes), D2Q9 flow + D2Q5 temperature populations, FP32
 storage in population rows, start at rest, walls +-0.5.  One "step" is one
 fused launch over the whole mesh.  Printed next to it: the same size on a
-uniform mesh (plain-shift kernel), HBM roofline of the dominant kernel, and
-the FP64 CPU oracle timed on the host cores over a bounded sample.
+uniform mesh (plain-shift kernel), the roofline of the dominant kernel (its
+working set fits the last-level cache, and says so), a 1 GiB device-copy
+ceiling, the FP64 instantiation on the headline mesh, the workloads beyond the
+cache (2-D 4096^2, 3-D 256^3 and 384^3 in FP32, 3-D 384^3 in FP16 and BF16,
+each beside its uniform mesh), a small learned-warm-start study (steps to a
+steady Nusselt number, warm against cold) and the FP64 CPU oracle timed on
+the host cores over a bounded sample (all cores and one thread).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--extra]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--headline-only] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -31,6 +36,10 @@ BYTES_PER_LU = {2: {"fp32": 112, "fp64": 224, "fp16": 56, "bf16": 56, "fp32sr": 
 KERNEL_SOURCES = ("paper_2509_01099_amd/csrc/islbm_kernels.hip",
                   "paper_2509_01099_amd/csrc/islbm_lattice.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_cosine1024_traffic.json")
+# workloads of --profile: (mesh kind, shape)
+PROFILE_MESHES = {"2d": ("cosine", (N_CFG, N_CFG)), "2d-4096": ("cosine", (4096, 4096)),
+                  "3d": ("tanh", (256, 256, 256)), "3d-384": ("tanh", (384, 384, 384)),
+                  "3d-uniform": ("uniform", (256, 256, 256))}
 
 
 def kernel_digest() -> str:
@@ -75,6 +84,87 @@ def time_run(cav, steps: int, warmup: int):
     return wall, ms / 1e3
 
 
+def time_run_split(cav, steps: int, warmup: int):
+    """As time_run, with the device time split at the final (reducing)
+    launch: returns (wall s, all launches s, plain launches s, reducing s)."""
+    import torch
+
+    cav.step(warmup)
+    cav.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot, plain, red = cav.time_steps_split(steps)   # HIP events on the launch stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, tot / 1e3, plain / 1e3, red / 1e3
+
+
+# Workloads beyond the 256 MB last-level cache (plus the uniform mesh of each
+# size): (label, mesh kind, shape, storage, timed launches)
+HBM_ROWS = (("2-D 4096^2 cosine, Ra 1e8", "cosine", (4096, 4096), "fp32", 300),
+            ("2-D 4096^2 uniform, Ra 1e8", "uniform", (4096, 4096), "fp32", 300),
+            ("3-D 256^3 tanh, Ra 1e7", "tanh", (256, 256, 256), "fp32", 200),
+            ("3-D 256^3 uniform, Ra 1e7", "uniform", (256, 256, 256), "fp32", 200),
+            ("3-D 384^3 tanh, Ra 1e7", "tanh", (384, 384, 384), "fp32", 100),
+            ("3-D 384^3 uniform, Ra 1e7", "uniform", (384, 384, 384), "fp32", 100),
+            ("3-D 384^3 tanh, Ra 1e7", "tanh", (384, 384, 384), "fp16", 100),
+            ("3-D 384^3 tanh, Ra 1e7", "tanh", (384, 384, 384), "bf16", 100))
+
+
+def step_row(label, kind, shape, storage, steps, warmup=10, copy_GBs=None, Ra=None):
+    """MLUPS and algorithmic bandwidth of one workload from the device time of
+    its plain launches (the final, reducing launch timed apart)."""
+    three = len(shape) == 3
+    Ra = Ra if Ra is not None else (1e7 if three else RA)
+    cav, _, _ = make_cavity(kind, shape, storage=storage, Ra=Ra,
+                            **({"u_f": 0.0} if three else {}))
+    _, _, plain, red = time_run_split(cav, steps, warmup)
+    bad = cav.stats(allow_nonfinite=True)["nonfinite"]
+    cav.close()
+    nodes = math.prod(shape)
+    per = plain / (steps - 1)
+    mlups = nodes / per / 1e6
+    gbs = BYTES_PER_LU[len(shape)][storage] * nodes / per / 1e9
+    row = {"workload": label, "storage": storage, "mlups": round(mlups, 1),
+           "bytes_per_update": BYTES_PER_LU[len(shape)][storage],
+           "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "avg_launch_us": round(per * 1e6, 2), "reducing_launch_us": round(red * 1e6, 2),
+           "nonfinite_nodes": bad}
+    if copy_GBs:
+        row["frac_of_copy"] = round(gbs / copy_GBs, 4)
+    return row
+
+
+def copy_ceiling(nbytes: int = 1 << 30, reps: int = 20) -> dict:
+    """Read + write bandwidth of 1 GiB device copies (the library's 16-byte
+    vector copy and torch's copy_), HIP events on the current stream."""
+    import torch
+
+    import paper_2509_01099_amd as pkg
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("vector16", lambda: pkg.islbm_copy_bytes(dst.data_ptr(), src.data_ptr(), nbytes,
+                                                              stream.cuda_stream)),
+                     ("torch_copy", lambda: dst.copy_(src))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        out[name] = round(2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+    ok = bool(torch.equal(dst, src))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_ceiling_GBs": max(out.values()), "copies_GBs": out, "bytes": nbytes,
+            "copy_verified": ok}
+
+
 def traffic_entry(dig: str):
     try:
         with open(TRAFFIC_FILE) as f:
@@ -86,14 +176,19 @@ def traffic_entry(dig: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(seconds_target: float = 15.0):
-    """The FP64 oracle, unmodified, on the host cores: a bounded sample of
-    the same workload (1024^2 cosine mesh, Ra 1e8, from rest)."""
-    import numpy as np
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        return "host CPU"
 
+
+def _oracle_mlups(threads: int, seconds: float):
+    """MLUPS of the unmodified FP64 oracle on the 1024^2 cosine workload
+    (Ra 1e8, from rest) with `threads` OpenMP threads, over about `seconds`."""
     import oracle
 
-    threads = min(16, os.cpu_count() or 1)
     oracle.set_threads(threads)
     x = oracle.mesh("cosine", N_CFG)
     x = x / (x[1] - x[0])
@@ -102,22 +197,37 @@ def cpu_baseline(seconds_target: float = 15.0):
     orc.run(1)
     steps, el = 0, 0.0
     t0 = time.perf_counter()
-    while el < seconds_target:
-        orc.run(2)
-        steps += 2
+    while el < seconds:
+        orc.run(1)
+        steps += 1
         el = time.perf_counter() - t0
-    mlups = N_CFG * N_CFG * steps / el / 1e6
-    del np
-    cpu = "host CPU"
+    used = oracle.get_threads()
+    del orc
+    return N_CFG * N_CFG * steps / el / 1e6, steps, el, used
+
+
+def cpu_baseline(seconds_all: float = 10.0, seconds_one: float = 8.0):
+    """The FP64 oracle, unmodified, on the host cores: a bounded sample of
+    the same workload (1024^2 cosine mesh, Ra 1e8, from rest), once on all
+    the cores this process may use (capped by OMP_NUM_THREADS when set) and
+    once on a single thread."""
+    nproc = os.cpu_count() or 1
     try:
-        with open("/proc/cpuinfo") as f:
-            cpu = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.get_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} steps of the 1024^2 cosine 2-D cavity (Ra 1e8, FP64) in "
-                      f"{el:.1f} s on {oracle.get_threads()} threads of {cpu}"}
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = nproc
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(allowed, int(omp)) if omp.isdigit() and int(omp) > 0 else allowed
+    cpu = _cpu_model()
+    m_all, s_all, e_all, used = _oracle_mlups(threads, seconds_all)
+    m_one, s_one, e_one, _ = _oracle_mlups(1, seconds_one)
+    return {"value": round(m_all, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"{s_all} steps of the 1024^2 cosine 2-D cavity (Ra 1e8, FP64) in "
+                      f"{e_all:.1f} s on {used} threads of {cpu}",
+            "single_thread": {"value": round(m_one, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": f"{s_one} steps in {e_one:.1f} s on 1 thread"},
+            "host": {"cpu_model": cpu, "nproc": nproc, "affinity_cpus": allowed,
+                     "OMP_NUM_THREADS": omp or None}}
 
 
 def precision_study(steps: int, n: int = 384, steady_steps: int = 1_600_000) -> dict:
@@ -687,9 +797,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200000)
     ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--extra", action="store_true",
-                    help="also time 4096^2 2-D and 256^3 3-D meshes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline and uniform lines (no copy ceiling, FP64 row, "
+                         "HBM rows or warm-start block)")
     ap.add_argument("--precision", type=int, default=0, metavar="STEPS",
                     help="reduced-precision storage study instead of the headline line: "
                          "3-D 384^3 tanh cavity, Ra 1e7, FP64/FP32/FP16/BF16, STEPS steps "
@@ -726,11 +837,14 @@ def main() -> int:
                     help="comma-separated mesh sizes of --convergence3d (default: the table's)")
     ap.add_argument("--validation3d", action="store_true",
                     help="steady 3-D cavity (129^3 erf, Ra 1e5, FP64) against the paper's table")
-    ap.add_argument("--profile-mesh", choices=["2d", "3d", "3d-uniform"], default="2d",
-                    help="workload of --profile: the 2-D benchmark mesh, the 3-D 256^3 tanh "
-                         "mesh (Ra 1e7) or the 3-D 256^3 uniform mesh")
+    ap.add_argument("--profile-mesh", choices=sorted(PROFILE_MESHES), default="2d",
+                    help="workload of --profile: 2d = the benchmark mesh (1024^2 cosine, Ra "
+                         "1e8), 2d-4096 = 4096^2 cosine, 3d = 256^3 tanh (Ra 1e7), 3d-384 = "
+                         "384^3 tanh, 3d-uniform = 256^3 uniform")
+    ap.add_argument("--profile-storage", choices=["fp32", "fp64", "fp16", "bf16", "fp32sr"],
+                    default="fp32", help="storage type of --profile")
     ap.add_argument("--profile", action="store_true",
-                    help="short run of the headline kernel only, plus a 1 GiB copy for "
+                    help="short run of one workload's step kernel only, plus a 1 GiB copy for "
                          "counter calibration (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -785,9 +899,9 @@ def main() -> int:
         return 0
 
     if args.profile:
-        shape = {"2d": n, "3d": (256, 256, 256), "3d-uniform": (256, 256, 256)}[args.profile_mesh]
-        kind = "uniform" if args.profile_mesh == "3d-uniform" else ("tanh" if len(shape) == 3 else "cosine")
-        cav, H, uf = make_cavity(kind, shape, Ra=RA if len(shape) == 2 else 1e7)
+        kind, shape = PROFILE_MESHES[args.profile_mesh]
+        cav, H, uf = make_cavity(kind, shape, storage=args.profile_storage,
+                                 Ra=RA if len(shape) == 2 else 1e7)
         nodes = math.prod(shape)
         wall, dev = time_run(cav, args.steps, args.warmup)
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -799,42 +913,36 @@ def main() -> int:
                           "copy_bytes": 1 << 30}))
         return 0
 
-    # headline: non-uniform (cosine) mesh
+    # headline: non-uniform (cosine) mesh, FP32
     cav, H, uf = make_cavity("cosine", n)
-    wall, dev = time_run(cav, args.steps, args.warmup)
+    wall, dev, dev_plain, dev_red = time_run_split(cav, args.steps, args.warmup)
     st = cav.stats(allow_nonfinite=True)
     cav.close()
     mlups = nodes * args.steps / wall / 1e6
-    per_launch = dev / args.steps
+    per_plain = dev_plain / (args.steps - 1) if args.steps > 1 else dev
     bpl = BYTES_PER_LU[2]["fp32"] * nodes
-    achieved = bpl / per_launch / 1e9
+    achieved = bpl / per_plain / 1e9
     dig = kernel_digest()
     traffic = traffic_entry(dig)
 
     # same size, uniform mesh (plain-shift kernel)
     ucav, uH, uuf = make_cavity("uniform", n)
-    uwall, udev = time_run(ucav, args.steps, args.warmup)
+    uwall, udev, udev_plain, _ = time_run_split(ucav, args.steps, args.warmup)
     ucav.close()
     umlups = nodes * args.steps / uwall / 1e6
+    uper = udev_plain / (args.steps - 1) if args.steps > 1 else udev
 
-    extra = []
-    if args.extra:
-        for kind, shape, storage, steps in (("cosine", (4096, 4096), "fp32", 2000),
-                                            ("uniform", (4096, 4096), "fp32", 2000),
-                                            ("tanh", (256, 256, 256), "fp32", 1000),
-                                            ("uniform", (256, 256, 256), "fp32", 1000)):
-            c, h, u = make_cavity(kind, shape, storage=storage,
-                                  Ra=1e7 if len(shape) == 3 else RA,
-                                  **({"u_f": 0.0} if len(shape) == 3 else {}))
-            w, d = time_run(c, steps, 50)
-            c.close()
-            nn = 1
-            for k in shape:
-                nn *= k
-            extra.append({"mesh": kind, "shape": list(shape), "storage": storage,
-                          "mlups": round(nn * steps / w / 1e6, 1),
-                          "achieved_GBs": round(BYTES_PER_LU[len(shape)][storage] * nn /
-                                                (d / steps) / 1e9, 1)})
+    copy = None if args.headline_only else copy_ceiling()
+    cgbs = copy["copy_ceiling_GBs"] if copy else None
+    rows, fp64_row, ws = [], None, None
+    if not args.headline_only:
+        fp64_row = step_row("2-D 1024^2 cosine, Ra 1e8 (FP64, the paper's precision)", "cosine",
+                            n, "fp64", 2000, copy_GBs=cgbs)
+        _log(f"fp64 row: {fp64_row}")
+        for label, kind, shape, storage, k in HBM_ROWS:
+            rows.append(step_row(label, kind, shape, storage, k, copy_GBs=cgbs))
+            _log(f"hbm row: {rows[-1]}")
+        ws = warmstart_block()
 
     cpu = None if args.no_cpu else cpu_baseline()
     out = {
@@ -858,15 +966,30 @@ def main() -> int:
                    "nonfinite_nodes": st["nonfinite"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "step_kernel<2,Tile<64,4,1,1>,float> (cache-resident class)",
-                     "bytes_per_launch": bpl, "avg_launch_us": round(per_launch * 1e6, 3)},
+                     "traffic": traffic,
+                     "kernel": "step_kernel<2,Tile<64,4,1,1>,float> (plain launches)",
+                     "cache_resident": True,
+                     "note": "the two FP32 buffers of the 1024^2 mesh (117 MB) fit the 256 MB "
+                             "last-level cache, so part of this traffic is served there; "
+                             "hbm_rows holds the workloads beyond the cache",
+                     "bytes_per_launch": bpl, "avg_launch_us": round(per_plain * 1e6, 3),
+                     "reducing_launch_us": round(dev_red * 1e6, 3),
+                     "mlups_plain_launches": round(nodes / per_plain / 1e6, 1)},
         "uniform": {"value": round(umlups, 1), "unit": "MLUPS",
                     "nonuniform_over_uniform": round(mlups / umlups, 4),
-                    "achieved_GBs": round(bpl / (udev / args.steps) / 1e9, 1)},
+                    "plain_launch_us": round(uper * 1e6, 3),
+                    "achieved_GBs": round(bpl / uper / 1e9, 1)},
         "cpu_baseline": cpu,
     }
-    if extra:
-        out["extra"] = extra
+    if copy:
+        out["copy_ceiling_GBs"] = cgbs
+        out["copies_GBs"] = copy["copies_GBs"]
+    if fp64_row:
+        out["fp64_row"] = fp64_row
+    if rows:
+        out["hbm_rows"] = rows
+    if ws:
+        out["warm_start"] = ws
     print(json.dumps(out))
     return 0
 

@@ -248,6 +248,20 @@ const char* islbm_last_error(const islbm_ctx* ctx);
  * and returns the elapsed milliseconds in *ms. */
 int islbm_time_steps(islbm_ctx* ctx, long long nsteps, double* ms);
 
+/* The same with the timed region split at the final launch (the one that also
+ * writes the reduction partials): *ms_total for all nsteps launches,
+ * *ms_plain for the nsteps - 1 plain launches before it, *ms_reduce for the
+ * reducing launch (ms_total - ms_plain).  nsteps >= 1.  Synchronises. */
+int islbm_time_steps_split(islbm_ctx* ctx, long long nsteps, double* ms_total, double* ms_plain,
+                           double* ms_reduce);
+
+/* Measurement helper, not part of the time step: copies `bytes` bytes from
+ * device buffer src to device buffer dst with 16-byte vector loads and stores
+ * (a streaming kernel's bandwidth ceiling on this device).  Both pointers
+ * 16-byte aligned, bytes a positive multiple of 16, buffers not overlapping;
+ * else ISLBM_EINVAL.  Asynchronous on `stream` (a hipStream_t, NULL = default). */
+int islbm_copy_bytes(void* dst, const void* src, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "islbm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ISLBM_ORACLE_LIB selects another build of the same source (the sanitizer
+# test runs the oracle pins against an AddressSanitizer build this way)
+_LIB = os.environ.get("ISLBM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 STATS = ("nu_vol", "nu_hot", "nu_cold", "nu_mid", "re_vol", "re_uv", "mass",
          "rho_sum", "umax", "vmax", "wmax", "nonfinite", "re_rms")
@@ -44,7 +46,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.environ.get("ISLBM_ORACLE_LIB") and (
+            not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
         build()
     lib = C.CDLL(_LIB)
     lib.oracle_create.restype = C.c_void_p

@@ -68,3 +68,19 @@ def backward(W, cache, dout, quant: bool = False):
             _, zprev = cache[i - 1]
             dz = (q(dz) @ q(W[i])) * dsilu(zprev)
     return gW, gb
+
+
+def adam(w, g, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8,
+         wd: float = 0.0):
+    """One Adam step (Kingma & Ba, 2015) with decoupled weight decay
+    (Loshchilov & Hutter, 2019) in FP64; returns the new (w, m, v).
+    m and v are the biased first and second moment estimates, corrected by
+    1 - b1^t and 1 - b2^t at step t (t counts from 1); the decay term wd * w
+    uses the parameters before the step."""
+    w, g, m, v = (np.asarray(a, dtype=np.float64) for a in (w, g, m, v))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    w = w - lr * (mhat / (np.sqrt(vhat) + eps) + wd * w)
+    return w, m, v

@@ -30,7 +30,7 @@ EXPORTS = ("islbm_default_options", "islbm_query_bytes", "islbm_mesh_spacing", "
            "islbm_init_fields_device", "islbm_info", "islbm_time", "islbm_set_time",
            "islbm_sync", "islbm_destroy", "islbm_strerror", "islbm_last_error",
            "islbm_time_steps", "islbm_state_bytes", "islbm_save_state", "islbm_load_state",
-           "islbm_steady_change")
+           "islbm_steady_change", "islbm_time_steps_split", "islbm_copy_bytes")
 
 
 class islbm_options(C.Structure):
@@ -103,6 +103,8 @@ def load() -> C.CDLL:
     lib.islbm_last_error.argtypes = [P]
     lib.islbm_last_error.restype = C.c_char_p
     lib.islbm_time_steps.argtypes = [P, C.c_longlong, _D]
+    lib.islbm_time_steps_split.argtypes = [P, C.c_longlong, _D, _D, _D]
+    lib.islbm_copy_bytes.argtypes = [P, P, C.c_size_t, P]
     lib.islbm_state_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
     lib.islbm_save_state.argtypes = [P, C.c_void_p, C.c_size_t]
     lib.islbm_load_state.argtypes = [P, C.c_void_p, C.c_size_t]
@@ -178,6 +180,23 @@ def islbm_time_steps(ctx, nsteps: int) -> float:
     ms = C.c_double()
     _check(load().islbm_time_steps(ctx, int(nsteps), C.byref(ms)), ctx)
     return ms.value
+
+
+def islbm_time_steps_split(ctx, nsteps: int) -> tuple:
+    """(ms of all nsteps launches, ms of the nsteps - 1 plain ones, ms of the
+    final reducing launch), from HIP events on the context's stream."""
+    tot, plain, red = C.c_double(), C.c_double(), C.c_double()
+    _check(load().islbm_time_steps_split(ctx, int(nsteps), C.byref(tot), C.byref(plain),
+                                         C.byref(red)), ctx)
+    return tot.value, plain.value, red.value
+
+
+def islbm_copy_bytes(dst_ptr: int, src_ptr: int, nbytes: int, stream=None) -> None:
+    """Device copy with 16-byte vectors (bandwidth ceiling measurement)."""
+    rc = load().islbm_copy_bytes(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), int(nbytes),
+                                 C.c_void_p(stream) if stream else None)
+    if rc != 0:
+        raise RuntimeError(f"islbm_copy_bytes failed with status {rc}")
 
 
 def islbm_nu_re(ctx, allow_nonfinite: bool = False) -> dict:
@@ -325,6 +344,9 @@ class Cavity:
 
     def time_steps(self, n: int) -> float:
         return islbm_time_steps(self.ctx, n)
+
+    def time_steps_split(self, n: int) -> tuple:
+        return islbm_time_steps_split(self.ctx, n)
 
     def stats(self, allow_nonfinite: bool = False) -> dict:
         return islbm_nu_re(self.ctx, allow_nonfinite)

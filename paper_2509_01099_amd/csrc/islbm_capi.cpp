@@ -46,7 +46,7 @@ struct islbm_ctx {
   long long snap_t = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   long long t = 0;
   int no_graph = 0;
   hipGraphExec_t graph = nullptr;
@@ -100,7 +100,16 @@ extern "C" void islbm_default_options(islbm_options* o) {
   o->storage = ISLBM_FP32;
 }
 
-static size_t elem_bytes(int storage) { return islbm::storage_elem_bytes(storage); }
+// Bytes of one stored population value: FP32 and FP32SR 4, FP64 8, FP16DEV
+// and BF16DEV 2.
+static size_t elem_bytes(int storage) {
+  switch (storage) {
+    case ISLBM_FP32: return 4;
+    case ISLBM_FP64: return 8;
+    case ISLBM_FP32SR: return 4;
+    default: return 2;
+  }
+}
 
 static int pitch_for(int n0, int storage) {
   const int align = (int)(256 / elem_bytes(storage));
@@ -181,6 +190,7 @@ static void release(islbm_ctx* c) {
   dfree(c->snap_part);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev2) (void)hipEventDestroy(c->ev2);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
@@ -462,7 +472,8 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
   if ((e = hipMalloc(&c->dres, islbm::kRedSlots * sizeof(double))) != hipSuccess) return bail(hipfail(c, e, "hipMalloc"));
   if ((e = hipHostMalloc(&c->hres, islbm::kRedSlots * sizeof(double), hipHostMallocDefault)) != hipSuccess)
     return bail(hipfail(c, e, "hipHostMalloc"));
-  if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess)
+  if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess ||
+      (e = hipEventCreate(&c->ev2)) != hipSuccess)
     return bail(hipfail(c, e, "hipEventCreate"));
   if ((e = hipMalloc(&c->rctr, 2 * sizeof(unsigned int))) != hipSuccess) return bail(hipfail(c, e, "hipMalloc(rctr)"));
   if ((e = islbm::launch_fill_zero(c->rctr, 2 * sizeof(unsigned int), c->stream)) != hipSuccess)
@@ -523,7 +534,9 @@ static hipError_t build_graph(islbm_ctx* c) {
   return e;
 }
 
-static int enqueue_steps(islbm_ctx* c, long long nsteps) {
+// mid (optional): an event recorded between the plain launches and the
+// final, reducing one.
+static int enqueue_steps(islbm_ctx* c, long long nsteps, hipEvent_t mid = nullptr) {
   if (nsteps <= 0) return ISLBM_OK;
   long long plain = nsteps - 1;  // the last launch reduces
   if (!c->no_graph && plain >= 2 * kGraphBatch) {
@@ -547,6 +560,7 @@ static int enqueue_steps(islbm_ctx* c, long long nsteps) {
     hipError_t e = one_step(c, false);
     if (e != hipSuccess) return hipfail(c, e, "step kernel");
   }
+  if (mid) HIPCHECK(c, hipEventRecord(mid, c->stream));
   hipError_t e = one_step(c, true);
   if (e != hipSuccess) return hipfail(c, e, "step kernel (reducing)");
   c->partials_valid = true;
@@ -570,6 +584,31 @@ extern "C" int islbm_time_steps(islbm_ctx* ctx, long long nsteps, double* ms) {
   HIPCHECK(ctx, hipEventElapsedTime(&f, ctx->ev0, ctx->ev1));
   *ms = f;
   return ISLBM_OK;
+}
+
+extern "C" int islbm_time_steps_split(islbm_ctx* ctx, long long nsteps, double* ms_total, double* ms_plain,
+                                      double* ms_reduce) {
+  if (!ctx || nsteps < 1 || !ms_total || !ms_plain || !ms_reduce) return ISLBM_EINVAL;
+  HIPCHECK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  int rc = enqueue_steps(ctx, nsteps, ctx->ev2);
+  if (rc != ISLBM_OK) return rc;
+  HIPCHECK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCHECK(ctx, hipEventSynchronize(ctx->ev1));
+  float tot = 0.f, plain = 0.f;
+  HIPCHECK(ctx, hipEventElapsedTime(&tot, ctx->ev0, ctx->ev1));
+  HIPCHECK(ctx, hipEventElapsedTime(&plain, ctx->ev0, ctx->ev2));
+  *ms_total = tot;
+  *ms_plain = plain;
+  *ms_reduce = double(tot) - double(plain);
+  return ISLBM_OK;
+}
+
+extern "C" int islbm_copy_bytes(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || bytes == 0 || (bytes & 15) || (reinterpret_cast<size_t>(dst) & 15) ||
+      (reinterpret_cast<size_t>(src) & 15))
+    return ISLBM_EINVAL;
+  hipError_t e = islbm::launch_copy16(dst, src, bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ISLBM_OK : ISLBM_EDEVICE;
 }
 
 extern "C" int islbm_sync(islbm_ctx* ctx) {

@@ -1056,15 +1056,6 @@ static hipError_t by_storage(int storage, int dim, Fn&& fn) {
   }
 }
 
-size_t storage_elem_bytes(int storage) {
-  switch (storage) {
-    case 0: return 4;
-    case 1: return 8;
-    case 4: return 4;
-    default: return 2;
-  }
-}
-
 template <int D, typename R, bool LARGE>
 static int blocks_for(const DevState& s) {
   int tiles[3];
@@ -1136,6 +1127,23 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
   const int nb = (int)((words + 255) / 256 < 65536 ? (words + 255) / 256 : 65536);
   hipLaunchKernelGGL(fill_zero_kernel, dim3(nb > 0 ? nb : 1), dim3(256), 0, st,
                      static_cast<unsigned int*>(p), words);
+  return hipGetLastError();
+}
+
+// Plain device copy with 16-byte vector loads and stores over a grid-stride
+// loop (a measured ceiling for streaming kernels; not part of the step).
+__global__ void __launch_bounds__(256) copy16_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                     size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  const size_t want = (n + 255) / 256;
+  const int nb = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  hipLaunchKernelGGL(copy16_kernel, dim3(nb), dim3(256), 0, st, static_cast<uint4*>(dst),
+                     static_cast<const uint4*>(src), n);
   return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ int step_blocks(const DevState& s);
 hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void* fout,
                        void* gout, bool reduce, double* partials, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
 // One population between a dense FP64 node array (x fastest) and its rows in
 // a population buffer: dst / src point at the population's first row (the
 // buffer plus pop * ps elements); flow = 1 for f (weights subtracted / added
@@ -66,6 +67,5 @@ hipError_t launch_reduce_state(const DevState& s, const void* f, const void* g, 
 hipError_t launch_finish(const double* partials, int nblocks, double* out, hipStream_t st);
 hipError_t launch_steady_change(const DevState& s, const void* f, const void* g, double* snap, int first,
                                 double* partials, hipStream_t st);
-size_t storage_elem_bytes(int storage);
 
 }  // namespace islbm

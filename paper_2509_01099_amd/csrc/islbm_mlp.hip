@@ -328,7 +328,9 @@ extern "C" int islbm_f32_to_bf16(const float* src, void* dst, size_t count, void
 extern "C" int islbm_mlp_adam(float* w, const float* g, float* m, float* v, void* wb, size_t count, float lr, float b1,
                               float b2, float eps, float wd, int t, void* stream) {
   if (!w || !g || !m || !v || count == 0 || t <= 0) return -1;
-  const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+  // bias corrections formed in double: 1 - b2^t loses most of its float
+  // digits to cancellation when b2 is close to 1
+  const float c1 = float(1.0 - pow((double)b1, (double)t)), c2 = float(1.0 - pow((double)b2, (double)t));
   hipLaunchKernelGGL(adam_kernel, dim3(grid_for((long long)count)), dim3(256), 0, (hipStream_t)stream, w, g, m, v,
                      static_cast<__bf16*>(wb), count, lr, b1, b2, eps, wd, c1, c2);
   return status(hipGetLastError());
