@@ -432,6 +432,19 @@ extern "C" int islbm_create(islbm_ctx** out, int lattice, const int n_in[3],
     c->own_stream = true;
   }
   islbm_query_bytes(lattice, n, opt.storage, &c->fbytes, &c->gbytes);
+  {
+    // the step kernels address a tile's rows (at most 6 z-planes and 6 rows
+    // of halo and tile) by 32-bit byte offsets from its first row
+    const double rows = dim == 3 ? 6.0 * n[1] + 6.0 : 6.0;
+    const double span = (rows * double(s.rsf) + double(s.pitch)) * double(elem_bytes(opt.storage));
+    // and form row offsets with 24-bit multiplies
+    const bool fits24 = s.rsf < (1LL << 24) && n[0] < (1 << 24) && n[1] < (1 << 24) && n[2] < (1 << 24) &&
+                        rows < double(1 << 24);
+    if (span >= 4294967296.0 || !fits24) {
+      c->err = "mesh too large: the rows of one tile exceed 32-bit offsets";
+      return bail(ISLBM_EINVAL);
+    }
+  }
   // read + write buffers of one step against the 256 MB last-level cache
   const size_t ws = 2 * (c->fbytes + c->gbytes);
   s.large = ws > (size_t(1) << 30) ? 2 : (ws > (size_t(192) << 20) ? 1 : 0);

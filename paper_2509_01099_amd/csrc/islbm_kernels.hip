@@ -61,24 +61,33 @@ struct Store<double> {
 //
 // The time step stores 2-byte values with stochastic rounding (st_dither):
 // the FP32 result is rounded up with probability equal to its distance from
-// the lower neighbour in units of the spacing, using 13 (FP16) or 16 (BF16)
-// random bits added below the kept mantissa bits before truncation.  With
-// round-to-nearest, a change smaller than half a spacing is lost every step
-// and slowly driven states stall; stochastic rounding keeps the expected
-// stored value equal to the FP32 one.  Other writers (initialisation,
-// uploads) round to nearest.
+// the lower neighbour in units of the spacing.  gfx950 does this in one
+// instruction (v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32) from a 32-bit random
+// word; measured on MI355X, the mean over random words of the rounded value
+// equals the FP32 value to sampling accuracy whichever 13 or 16 of the word's
+// bits are random, i.e. the rounding is unbiased.  With round-to-nearest, a
+// change smaller than half a spacing is lost every step and slowly driven
+// states stall; stochastic rounding keeps the expected stored value equal to
+// the FP32 one.  Other writers (initialisation, uploads) round to nearest.
+typedef __fp16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 template <>
 struct Store<__half> {
   using R = float;
   static constexpr bool kDither = true;
   static constexpr float kScale = 4096.0f, kInv = 1.0f / 4096.0f;
   __device__ static float ld(const __half* p) { return __half2float(*p) * kInv; }
+  // two x-neighbours loaded as one 4-byte word (lower address in the low half)
+  __device__ static void unpack(unsigned w, float& lo, float& hi) {
+    lo = __half2float(__ushort_as_half((unsigned short)(w & 0xFFFFu))) * kInv;
+    hi = __half2float(__ushort_as_half((unsigned short)(w >> 16))) * kInv;
+  }
   __device__ static void st(__half* p, float v) { *p = __float2half_rn(v * kScale); }
   __device__ static void st_nt(__half* p, float v) { st(p, v); }
   __device__ static void st_dither(__half* p, float v, unsigned bits) {
-    unsigned u = __float_as_uint(v * kScale);
-    u = (u + (bits >> 19)) & ~0x1FFFu;  // exact in FP16 across its normal range
-    *p = __float2half_rn(__uint_as_float(u));
+    f16x2_t h = {0, 0};
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, v * kScale, bits, false);
+    *reinterpret_cast<__fp16*>(p) = h.x;
   }
 };
 template <>
@@ -86,30 +95,19 @@ struct Store<__hip_bfloat16> {
   using R = float;
   static constexpr bool kDither = true;
   __device__ static float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+  // a bfloat16 is the upper half of the float with the same bits
+  __device__ static void unpack(unsigned w, float& lo, float& hi) {
+    lo = __uint_as_float(w << 16);
+    hi = __uint_as_float(w & 0xFFFF0000u);
+  }
   __device__ static void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
   __device__ static void st_nt(__hip_bfloat16* p, float v) { st(p, v); }
   __device__ static void st_dither(__hip_bfloat16* p, float v, unsigned bits) {
-    unsigned u = __float_as_uint(v);
-    u = (u + (bits >> 16)) & 0xFFFF0000u;  // the kept upper half is the bfloat16
-    *p = __float2bfloat16(__uint_as_float(u));
+    bf16x2_t h = {0, 0};
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, bits, false);
+    *reinterpret_cast<__bf16*>(p) = h.x;
   }
 };
-
-// p + off with the byte offset formed in 32 bits.  With p uniform over the
-// workgroup, the access takes a scalar base plus a 32-bit vector offset
-// instead of a 64-bit vector address (fewer address instructions).  Used by
-// the cache-resident class of launches, where it measured faster; the
-// large class keeps 64-bit addressing, which measured faster there.  The
-// cache-resident class (FP32, FP16, BF16 storage) has both population
-// buffers below 192 MB, so no offset within them reaches 2^32 bytes.
-template <typename S>
-__device__ __forceinline__ const S* at(const S* p, unsigned off) {
-  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(p) + off * unsigned(sizeof(S)));
-}
-template <typename S>
-__device__ __forceinline__ S* at(S* p, unsigned off) {
-  return reinterpret_cast<S*>(reinterpret_cast<char*>(p) + off * unsigned(sizeof(S)));
-}
 
 // FP32 storage with FP64 arithmetic: the same 4-byte deviations as FP32,
 // loaded into double, updated in double, and written back with stochastic
@@ -145,10 +143,14 @@ __device__ __forceinline__ unsigned mix32(unsigned x) {
   return x;
 }
 
-// Store of population i of a node whose hash is h0.
+// Store of population i of a node whose hash is h0.  The rounding bits of
+// population i are the low 32 bits of the product of h0's low 24 bits and a
+// distinct odd 24-bit constant (a full-rate 24-bit multiply); st_dither takes
+// them from the high end, where every bit of the multiplicand contributes.
 template <typename S, bool NTS>
 __device__ __forceinline__ void store_pop(S* p, typename Store<S>::R v, unsigned h0, int i) {
-  if constexpr (Store<S>::kDither) Store<S>::st_dither(p, v, h0 * (unsigned(2 * i + 1) * 0x9E3779B1u));
+  if constexpr (Store<S>::kDither)
+    Store<S>::st_dither(p, v, __umul24(h0, (unsigned(2 * i + 1) * 0x9E3779B1u) & 0xFFFFFFu));
   else if constexpr (NTS) Store<S>::st_nt(p, v);
   else Store<S>::st(p, v);
 }
@@ -233,13 +235,17 @@ __device__ __forceinline__ unsigned dither_key(const KArgs<R>& a) {
 // ---------------------------------------------------------------------------
 // Tile geometry and LDS slots (one per moving population)
 // ---------------------------------------------------------------------------
-template <int TX_, int TY_, int TZ_, int NR_>
+// XH: x extent added to the tile by the halo of an x-shifted population: 2
+// (one node each side), or 4 for 2-byte storage, whose staged boxes start at
+// an even x so that they are loaded as 4-byte x pairs.
+template <int TX_, int TY_, int TZ_, int NR_, int XH_ = 2>
 struct Tile {
-  static constexpr int TX = TX_, TY = TY_, TZ = TZ_, NR = NR_;
+  static constexpr int TX = TX_, TY = TY_, TZ = TZ_, NR = NR_, XH = XH_;
   static constexpr int ROWS = TY * TZ;       // (y,z) rows of a tile
   static constexpr int RS = ROWS / NR;       // rows covered by one pass of the block
   static constexpr int NT = TX * RS;         // threads per block
   static_assert(ROWS % NR == 0, "rows per thread must divide the tile");
+  static_assert(XH == 2 || (XH == 4 && TX % 2 == 0), "paired staging needs an even tile width");
   __host__ __device__ static constexpr int ext(int a) { return a == 0 ? TX : (a == 1 ? TY : TZ); }
 };
 
@@ -253,7 +259,9 @@ struct Slots {
   __host__ __device__ static constexpr int e(int s, int a) {
     return isg(s) ? LG::e(pop(s), a) : LF::e(pop(s), a);
   }
-  __host__ __device__ static constexpr int ext(int s, int a) { return T::ext(a) + (e(s, a) != 0 ? 2 : 0); }
+  __host__ __device__ static constexpr int ext(int s, int a) {
+    return T::ext(a) + (e(s, a) != 0 ? (a == 0 ? T::XH : 2) : 0);
+  }
   __host__ __device__ static constexpr int size(int s) { return ext(s, 0) * ext(s, 1) * ext(s, 2); }
   __host__ __device__ static constexpr int off(int s) {
     int o = 0;
@@ -293,69 +301,139 @@ __device__ __forceinline__ TileOrigin tile_origin(const int* n, const int* tiles
   o.t0[2] = bz * T::TZ;
 #pragma unroll
   for (int a = 0; a < 3; ++a) o.lo[a] = n[a] >= 3 ? clampi(o.t0[a] - 1, 0, n[a] - 3) : o.t0[a];
+  if constexpr (T::XH == 4) o.lo[0] &= ~1;  // paired staging: boxes start at an even x
   return o;
 }
 
-// Staging of the tiles into LDS.  Every thread first issues all of its
-// global loads (a compile-time number per slot) into registers, and only then
-// writes them to LDS, so that a workgroup has its whole tile in flight at once
-// instead of one round trip per loop iteration.
+// Staging of the tiles into LDS.
+// The box a slot stages depends only on the axes its population is shifted
+// along (its "shape": a bit per axis), so every slot of one shape and one
+// population set has the same per-thread element offsets.  A thread forms
+// those offsets once per shape (plan_shape: byte offsets relative to the
+// tile's first halo row R0, 32 bits), and each slot's loads are then a
+// workgroup-uniform base address plus these offsets, with no per-element index
+// arithmetic.  2-byte storage stages x pairs: one 4-byte load per two
+// elements, boxes starting at an even x.  Every thread first issues all of
+// its global loads into registers, and only then writes them to LDS, so that
+// a workgroup has its whole tile in flight at once.
 template <int D, class T>
-struct Staging {
+struct Shapes {
   using SL = Slots<D, T>;
-  __host__ __device__ static constexpr int iters(int s) { return (SL::size(s) + T::NT - 1) / T::NT; }
+  static constexpr int U = T::XH == 4 ? 2 : 1;  // elements per load unit
+  __host__ __device__ static constexpr int of(int s) {
+    return (SL::e(s, 0) != 0 ? 1 : 0) | (SL::e(s, 1) != 0 ? 2 : 0) | (SL::e(s, 2) != 0 ? 4 : 0);
+  }
+  __host__ __device__ static constexpr int ext(int m, int a) {
+    return T::ext(a) + (((m >> a) & 1) ? (a == 0 ? T::XH : 2) : 0);
+  }
+  __host__ __device__ static constexpr int units(int m) { return ext(m, 0) / U * ext(m, 1) * ext(m, 2); }
+  __host__ __device__ static constexpr int iters(int m) { return (units(m) + T::NT - 1) / T::NT; }
+  // shape m is staged by some slot of the thermal (g) or flow (!g) set
+  __host__ __device__ static constexpr bool used(int m, bool g) {
+    for (int s = 0; s < SL::N; ++s)
+      if (SL::isg(s) == g && of(s) == m) return true;
+    return false;
+  }
+  // first offset of shape m in the set's offset array, and their number
+  __host__ __device__ static constexpr int ooff(int m, bool g) {
+    int o = 0;
+    for (int k = 0; k < m; ++k)
+      if (used(k, g)) o += iters(k);
+    return o;
+  }
+  __host__ __device__ static constexpr int noff(bool g) { return ooff(8, g) > 0 ? ooff(8, g) : 1; }
+  // staging registers of slot s (one per load unit)
   __host__ __device__ static constexpr int roff(int s) {
     int o = 0;
-    for (int k = 0; k < s; ++k) o += iters(k);
+    for (int k = 0; k < s; ++k) o += iters(of(k));
     return o;
   }
   static constexpr int total = roff(SL::N);
 };
 
-template <int D, class T, int s, bool OFF32, typename S, typename R>
-__device__ __forceinline__ void issue_slot(R* regs, const S* __restrict__ fin, const S* __restrict__ gin,
-                                           const KArgs<R>& a, const TileOrigin& o) {
-  using SL = Slots<D, T>;
-  using ST = Staging<D, T>;
-  constexpr int W = SL::ext(s, 0), H = SL::ext(s, 1), V = SL::size(s);
-  const int ox = SL::e(s, 0) ? o.lo[0] : o.t0[0];
-  const int oy = SL::e(s, 1) ? o.lo[1] : o.t0[1];
-  const int oz = SL::e(s, 2) ? o.lo[2] : o.t0[2];
-  // OFF32: base at the slot's first (y, z) row, 32-bit offsets from it
-  const long long rs = SL::isg(s) ? a.rsg : a.rsf;
-  const S* src = (SL::isg(s) ? gin : fin) + (long long)SL::pop(s) * a.ps +
-                 (OFF32 ? ((long long)oz * a.n[1] + oy) * rs : 0LL);
+// byte address base + off (off a 32-bit byte offset): with a workgroup-uniform
+// base the access takes a scalar base and a 32-bit vector offset
+__device__ __forceinline__ const char* atb(const char* base, unsigned off) { return base + off; }
+__device__ __forceinline__ char* atb(char* base, unsigned off) { return base + off; }
+
+template <int D, class T, typename S, typename R, int m>
+__device__ __forceinline__ void plan_shape(unsigned* offf, unsigned* offg, const KArgs<R>& a,
+                                           const TileOrigin& o, unsigned R0) {
+  using SH = Shapes<D, T>;
+  constexpr bool UF = SH::used(m, false), UG = SH::used(m, true);
+  if constexpr (UF || UG) {
+    constexpr int U = SH::U, W = SH::ext(m, 0) / U, H = SH::ext(m, 1), V = SH::units(m);
+    const int ox = (m & 1) ? o.lo[0] : o.t0[0];
+    const int oy = (m & 2) ? o.lo[1] : o.t0[1];
+    const int oz = (m & 4) ? o.lo[2] : o.t0[2];
+    // last load unit of a row: a pair never starts beyond the last even x
+    // (its second element then lies in the row padding, or is the last node)
+    const int xmax = U == 2 ? ((a.n[0] - 1) & ~1) : a.n[0] - 1;
 #pragma unroll
-  for (int k = 0; k < ST::iters(s); ++k) {
-    // Branch-free: positions beyond the slot or the mesh are clamped to a
-    // valid node; those LDS entries are never read by a pull.
-    int idx = threadIdx.x + k * T::NT;
-    if (V % T::NT != 0 && k + 1 == ST::iters(s)) idx = idx < V ? idx : V - 1;
-    const int lz = idx / (W * H);
-    const int rem = idx - lz * (W * H);
-    const int ly = rem / W;
-    const int lx = rem - ly * W;
-    const int gx = min(ox + lx, a.n[0] - 1);
-    const int gy = min(oy + ly, a.n[1] - 1);
-    const int gz = min(oz + lz, a.n[2] - 1);
-    if constexpr (OFF32)
-      regs[ST::roff(s) + k] = Store<S>::ld(
-          at(src, (unsigned(gz - oz) * unsigned(a.n[1]) + unsigned(gy - oy)) * unsigned(rs) + unsigned(gx)));
-    else
-      regs[ST::roff(s) + k] = Store<S>::ld(src + ((long long)gz * a.n[1] + gy) * rs + gx);
+    for (int k = 0; k < SH::iters(m); ++k) {
+      // Branch-free: positions beyond the box or the mesh are clamped to a
+      // valid node; those LDS entries are never read by a pull.
+      int idx = threadIdx.x + k * T::NT;
+      if (V % T::NT != 0 && k + 1 == SH::iters(m)) idx = idx < V ? idx : V - 1;
+      const int lz = idx / (W * H);
+      const int rem = idx - lz * (W * H);
+      const int ly = rem / W;
+      const int lx = rem - ly * W;
+      const unsigned gx = unsigned(min(ox + lx * U, xmax));
+      const unsigned gy = unsigned(min(oy + ly, a.n[1] - 1));
+      const unsigned gz = unsigned(min(oz + lz, a.n[2] - 1));
+      // 24-bit multiplies (full rate): node counts per axis, rows of a tile's
+      // span and row strides are all below 2^24
+      const unsigned row = __umul24(gz, unsigned(a.n[1])) + gy - R0;
+      if constexpr (UF) offf[SH::ooff(m, false) + k] = (__umul24(row, unsigned(a.rsf)) + gx) * unsigned(sizeof(S));
+      if constexpr (UG) offg[SH::ooff(m, true) + k] = (__umul24(row, unsigned(a.rsg)) + gx) * unsigned(sizeof(S));
+    }
   }
 }
 
-template <int D, class T, int s, typename R>
-__device__ __forceinline__ void commit_slot(R* lds, const R* regs) {
+// One load unit: the stored value (converted), or for paired staging the raw
+// 4 bytes of two x-neighbours.
+template <typename S, bool PAIR>
+struct Unit {
+  using type = std::conditional_t<PAIR, unsigned, typename Store<S>::R>;
+  __device__ static type ld(const char* p) {
+    if constexpr (PAIR) return *reinterpret_cast<const unsigned*>(p);
+    else return Store<S>::ld(reinterpret_cast<const S*>(p));
+  }
+};
+
+template <int D, class T, int s, typename S, typename W, typename R>
+__device__ __forceinline__ void issue_slot(W* regs, const char* fb, const char* gb, const unsigned* offf,
+                                           const unsigned* offg, const KArgs<R>& a) {
   using SL = Slots<D, T>;
-  using ST = Staging<D, T>;
-  constexpr int V = SL::size(s);
+  using SH = Shapes<D, T>;
+  constexpr int m = SH::of(s);
+  constexpr bool g = SL::isg(s);
+  const char* base = (g ? gb : fb) + (long long)SL::pop(s) * a.ps * (long long)sizeof(S);
+  const unsigned* off = (g ? offg : offf) + SH::ooff(m, g);
+#pragma unroll
+  for (int k = 0; k < SH::iters(m); ++k)
+    regs[SH::roff(s) + k] = Unit<S, (T::XH == 4)>::ld(atb(base, off[k]));
+}
+
+template <int D, class T, int s, typename S, typename W, typename R>
+__device__ __forceinline__ void commit_slot(R* lds, const W* regs) {
+  using SL = Slots<D, T>;
+  using SH = Shapes<D, T>;
+  constexpr int m = SH::of(s), V = SH::units(m);
   R* dst = lds + SL::off(s);
 #pragma unroll
-  for (int k = 0; k < ST::iters(s); ++k) {
+  for (int k = 0; k < SH::iters(m); ++k) {
     const int idx = threadIdx.x + k * T::NT;
-    if (V % T::NT == 0 || k + 1 < ST::iters(s) || idx < V) dst[idx] = regs[ST::roff(s) + k];
+    if (V % T::NT == 0 || k + 1 < SH::iters(m) || idx < V) {
+      if constexpr (T::XH == 4) {
+        R lo, hi;
+        Store<S>::unpack(regs[SH::roff(s) + k], lo, hi);
+        reinterpret_cast<float2*>(dst)[idx] = make_float2(lo, hi);
+      } else {
+        dst[idx] = regs[SH::roff(s) + k];
+      }
+    }
   }
 }
 
@@ -528,26 +606,56 @@ __device__ __forceinline__ void red_block(RedAcc& r, double* out) {
 // ---------------------------------------------------------------------------
 // The fused time step
 // ---------------------------------------------------------------------------
+// Per-axis weights of node j: the three weights of direction +1 (table row j)
+// and of direction -1 (row n + j), each row padded to four entries, so one
+// 16-byte (FP32) or two 16-byte (FP64) loads per row.
+template <typename R>
+__device__ __forceinline__ void load_weights(const R* tab, int n, int j, R* wp, R* wm) {
+  if constexpr (std::is_same_v<R, float>) {
+    const float4 p = reinterpret_cast<const float4*>(tab)[j];
+    const float4 m = reinterpret_cast<const float4*>(tab)[n + j];
+    wp[0] = p.x, wp[1] = p.y, wp[2] = p.z;
+    wm[0] = m.x, wm[1] = m.y, wm[2] = m.z;
+  } else {
+    const double2* t = reinterpret_cast<const double2*>(tab);
+    const double2 p0 = t[2 * j], p1 = t[2 * j + 1], m0 = t[2 * (n + j)], m1 = t[2 * (n + j) + 1];
+    wp[0] = p0.x, wp[1] = p0.y, wp[2] = p1.x;
+    wm[0] = m0.x, wm[1] = m0.y, wm[2] = m1.x;
+  }
+}
+
 template <int D, class T, typename S, bool UNI, bool REDUCE, bool COLLIDE, bool NTS>
 __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, const S* __restrict__ gin,
                                                      S* __restrict__ fout, S* __restrict__ gout,
                                                      KArgs<typename Store<S>::R> a) {
   using R = typename Store<S>::R;
   using SL = Slots<D, T>;
+  using SH = Shapes<D, T>;
   using LF = typename SL::LF;
   using LG = typename SL::LG;
-  __shared__ R lds[SL::total];
+  using W = typename Unit<S, (T::XH == 4)>::type;
+  __shared__ __align__(16) R lds[SL::total];
   const unsigned dkey = dither_key<S>(a);
-  // cache-resident class with FP32 arithmetic: scalar base + 32-bit offsets
-  // (FP64 arithmetic always takes 64-bit addresses)
-  constexpr bool OFF32 = !NTS && std::is_same_v<R, float>;
 
   const TileOrigin o = tile_origin<T>(a.n, a.tiles, a.nblocks);
-  // 1. issue every global load of the tile (moving populations into staging
-  //    registers, rest populations and this thread's x weights directly)
-  R regs[Staging<D, T>::total];
+  // Every global address of the launch is a workgroup-uniform base at the
+  // tile's first halo row R0 plus a 32-bit byte offset (the library checks
+  // at create that a tile's span of rows fits 32-bit offsets).
+  const unsigned R0 = unsigned(o.lo[2]) * unsigned(a.n[1]) + unsigned(o.lo[1]);
+  constexpr long long SB = sizeof(S);
+  const char* fb = reinterpret_cast<const char*>(fin) + (long long)R0 * a.rsf * SB;
+  const char* gb = reinterpret_cast<const char*>(gin) + (long long)R0 * a.rsg * SB;
+
+  // 1. staging offsets, once per shape; then every global load of the tile
+  //    (moving populations into staging registers, rest populations and
+  //    weights directly)
+  unsigned offf[SH::noff(false)], offg[SH::noff(true)];
+  [&]<int... MM>(std::integer_sequence<int, MM...>) {
+    (plan_shape<D, T, S, R, MM>(offf, offg, a, o, R0), ...);
+  }(std::make_integer_sequence<int, 8>{});
+  W regs[SH::total];
   [&]<int... SS>(std::integer_sequence<int, SS...>) {
-    (issue_slot<D, T, SS, OFF32, S, R>(regs, fin, gin, a, o), ...);
+    (issue_slot<D, T, SS, S>(regs, fb, gb, offf, offg, a), ...);
   }(std::make_integer_sequence<int, SL::N>{});
 
   const int lx = threadIdx.x % T::TX;
@@ -563,17 +671,13 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   }
   if (!UNI && xin) {
     q.base[0] = clampi(q.g[0] - 1, 0, a.n[0] - 3) - o.lo[0];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      q.wp[0][c] = a.wtab[0][(long long)q.g[0] * 4 + c];
-      q.wm[0][c] = a.wtab[0][((long long)a.n[0] + q.g[0]) * 4 + c];
-    }
+    load_weights(a.wtab[0], a.n[0], q.g[0], q.wp[0], q.wm[0]);
   }
-  // node (lx, ly, lz) of the tile: row trow + (lz, ly) of the tile; with
-  // OFF32 the address is the tile's first row plus a 32-bit offset
-  const long long trow = (long long)o.t0[2] * a.n[1] + o.t0[1];
-  auto toff = [&](int ly, int lz, long long rs) {
-    return (unsigned(lz) * unsigned(a.n[1]) + unsigned(ly)) * unsigned(rs) + unsigned(q.g[0]);
+  // byte offset of node (x, row (ly, lz) of the tile) from R0 in a set with
+  // row stride rs
+  auto noff = [&](int ly, int lz, long long rs) {
+    const unsigned row = __umul24(unsigned(o.t0[2] + lz), unsigned(a.n[1])) + unsigned(o.t0[1] + ly) - R0;
+    return (__umul24(row, unsigned(rs)) + unsigned(q.g[0])) * unsigned(SB);
   };
   R rest_f[T::NR], rest_g[T::NR];
 #pragma unroll
@@ -584,24 +688,20 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
     rest_f[k] = R(0);
     rest_g[k] = R(0);
     if (xin && gy < a.n[1] && gz < a.n[2]) {
-      if constexpr (OFF32) {
-        rest_f[k] = Store<S>::ld(at(fin + trow * a.rsf, toff(ly, lz, a.rsf)));
-        rest_g[k] = Store<S>::ld(at(gin + trow * a.rsg, toff(ly, lz, a.rsg)));
-      } else {
-        const long long mrow = (long long)gz * a.n[1] + gy;
-        rest_f[k] = Store<S>::ld(fin + mrow * a.rsf + q.g[0]);
-        rest_g[k] = Store<S>::ld(gin + mrow * a.rsg + q.g[0]);
-      }
+      rest_f[k] = Store<S>::ld(reinterpret_cast<const S*>(atb(fb, noff(ly, lz, a.rsf))));
+      rest_g[k] = Store<S>::ld(reinterpret_cast<const S*>(atb(gb, noff(ly, lz, a.rsg))));
     }
   }
   // 2. write the staged tiles to LDS
   [&]<int... SS>(std::integer_sequence<int, SS...>) {
-    (commit_slot<D, T, SS, R>(lds, regs), ...);
+    (commit_slot<D, T, SS, S>(lds, regs), ...);
   }(std::make_integer_sequence<int, SL::N>{});
   __syncthreads();
 
   RedAcc acc;
   if constexpr (REDUCE) red_init(acc);
+  char* fo = reinterpret_cast<char*>(fout) + (long long)R0 * a.rsf * SB;
+  char* go = reinterpret_cast<char*>(gout) + (long long)R0 * a.rsg * SB;
 
 #pragma unroll 1
   for (int k = 0; k < T::NR; ++k) {
@@ -624,11 +724,7 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
 #pragma unroll
       for (int ax = 1; ax < D; ++ax) {
         q.base[ax] = clampi(q.g[ax] - 1, 0, a.n[ax] - 3) - o.lo[ax];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          q.wp[ax][c] = a.wtab[ax][(long long)q.g[ax] * 4 + c];
-          q.wm[ax][c] = a.wtab[ax][((long long)a.n[ax] + q.g[ax]) * 4 + c];
-        }
+        load_weights(a.wtab[ax], a.n[ax], q.g[ax], q.wp[ax], q.wm[ax]);
       }
     }
     R d[LF::Q], g[LG::Q];
@@ -650,21 +746,16 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
     const long long mrow = (long long)q.g[2] * a.n[1] + q.g[1];
     // rounding bits keyed by the node (its index in a row-pitched mesh)
     const unsigned h0 = Store<S>::kDither ? mix32(unsigned(mrow * a.pitch + q.g[0]) ^ dkey) : 0u;
-    if constexpr (OFF32) {
-      const unsigned clf = toff(ly, lz, a.rsf), clg = toff(ly, lz, a.rsg);
+    // population i lies i rows of ps elements further (a few MB at most, so
+    // the whole offset stays a 32-bit vector offset from the uniform base)
+    const unsigned cf = noff(ly, lz, a.rsf), cg = noff(ly, lz, a.rsg);
+    const unsigned prow = unsigned(a.ps) * unsigned(SB);
 #pragma unroll
-      for (int i = 0; i < LF::Q; ++i)
-        store_pop<S, NTS>(at(fout + (trow * a.rsf + (long long)i * a.ps), clf), d[i], h0, i);
+    for (int i = 0; i < LF::Q; ++i)
+      store_pop<S, NTS>(reinterpret_cast<S*>(atb(fo, cf + unsigned(i) * prow)), d[i], h0, i);
 #pragma unroll
-      for (int i = 0; i < LG::Q; ++i)
-        store_pop<S, NTS>(at(gout + (trow * a.rsg + (long long)i * a.ps), clg), g[i], h0, 32 + i);
-    } else {
-      const long long cf = mrow * a.rsf + q.g[0], cg = mrow * a.rsg + q.g[0];
-#pragma unroll
-      for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(fout + (long long)i * a.ps + cf, d[i], h0, i);
-#pragma unroll
-      for (int i = 0; i < LG::Q; ++i) store_pop<S, NTS>(gout + (long long)i * a.ps + cg, g[i], h0, 32 + i);
-    }
+    for (int i = 0; i < LG::Q; ++i)
+      store_pop<S, NTS>(reinterpret_cast<S*>(atb(go, cg + unsigned(i) * prow)), g[i], h0, 32 + i);
   }
   if constexpr (REDUCE) {
     const int lb = blockIdx.x;
@@ -961,19 +1052,27 @@ static int grid_of(const DevState& s, int* tiles) {
   return tiles[0] * tiles[1] * tiles[2];
 }
 
-// 2-byte storage in 2-D keeps the short 64 x 4 tiles also for large meshes
-// (measured 13 % faster there than 64 x 8 tiles with two rows per thread).
+// 2-byte storage stages x pairs (Tile XH = 4) and in 2-D keeps the short
+// 64 x 4 tiles also for large meshes (measured 13 % faster there than 64 x 8
+// tiles with two rows per thread).
+template <class T>
+struct Paired;
+template <int TX, int TY, int TZ, int NR, int XH>
+struct Paired<Tile<TX, TY, TZ, NR, XH>> {
+  using type = Tile<TX, TY, TZ, NR, 4>;
+};
 template <int D, typename S, bool LARGE>
 struct TileSel {
-  using T = typename TileFor<D, typename Store<S>::R, LARGE>::T;
+  using T0 = typename TileFor<D, typename Store<S>::R, LARGE>::T;
+  using T = std::conditional_t<sizeof(S) == 2, typename Paired<T0>::type, T0>;
 };
-template <>
-struct TileSel<2, __half, true> {
-  using T = Tile<64, 4, 1, 1>;
+template <bool L>
+struct TileSel<2, __half, L> {
+  using T = Tile<64, 4, 1, 1, 4>;
 };
-template <>
-struct TileSel<2, __hip_bfloat16, true> {
-  using T = Tile<64, 4, 1, 1>;
+template <bool L>
+struct TileSel<2, __hip_bfloat16, L> {
+  using T = Tile<64, 4, 1, 1, 4>;
 };
 
 template <int D, typename S, bool LARGE, bool UNI, bool RED, bool COL>

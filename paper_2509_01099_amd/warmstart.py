@@ -271,9 +271,16 @@ class WarmStartMLP:
 
 # ------------------------------------------------------------- study driver
 
-def draw_ra(count: int = 40, seed: int = 2025, lo: float = 6.0, hi: float = 8.0) -> np.ndarray:
-    """Rayleigh numbers log-uniform in [10^lo, 10^hi] from a seed."""
-    return 10.0 ** np.random.default_rng(seed).uniform(lo, hi, count)
+def draw_ra(count: int = 40, seed: int = 2025, lo: float = 6.0, hi: float = 8.0,
+            stratified: bool = False) -> np.ndarray:
+    """Rayleigh numbers log-uniform in [10^lo, 10^hi] from a seed.  With
+    stratified=True the k-th draw is uniform in the k-th of `count` equal
+    sub-intervals of [lo, hi] (each draw is still log-uniform over the whole
+    range when k is picked at random; the set covers the range evenly)."""
+    u = np.random.default_rng(seed).uniform(0.0, 1.0, count)
+    if stratified:
+        u = (np.arange(count) + u) / count
+    return 10.0 ** (lo + (hi - lo) * u)
 
 
 def mesh_spacing(kind: str = "erf", n: int = 513, a: float = 1.5) -> np.ndarray:
@@ -374,3 +381,79 @@ def predict_init(net: "WarmStartMLP", cav, sp: np.ndarray, Ra: float, uf: float)
     torch.cuda.synchronize()
     islbm_init_fields_device(cav.ctx, u, v, w, T)
     cav.sync()  # u, v, w, T are released when this returns
+
+
+def quick_study(n: int = 129, n_train: int = 10, n_held: int = 3, steps: int = 600_000,
+                chunk: int = 10_000, train_steps: int = 8000, lo: float = 6.0, hi: float = 7.0,
+                seed: int = 11, storage: str = "fp64", log=None) -> dict:
+    """Learned warm start end to end on a small 2-D cavity (n^2 erf mesh,
+    a = 1.5, Pr 0.71, Ma 0.1): cold solves from rest at n_train training and
+    n_held held-out Rayleigh numbers (log-uniform in [10^lo, 10^hi], drawn
+    from two seeds), all run concurrently; the network is trained on the
+    training fields; the held-out cavities are then run again from the
+    network's prediction.  The training Ra are stratified draws (one per
+    equal sub-interval of log10 Ra), the held-out Ra plain draws from the
+    next seed.  For each held-out Ra: steps until Nu_hot stays
+    within 1e-3 of the cold run's final value (recorded every `chunk` steps),
+    cold and warm, and the relative Nu_hot difference of the two final states."""
+    import time
+
+    import torch
+
+    from . import Cavity
+
+    t0 = time.perf_counter()
+    sp = mesh_spacing("erf", n, 1.5)
+    train_ra = [float(r) for r in draw_ra(n_train, seed=seed, lo=lo, hi=hi, stratified=True)]
+    held_ra = [float(r) for r in draw_ra(n_held, seed=seed + 1, lo=lo, hi=hi)]
+    uf = 0.1 / 3 ** 0.5
+
+    def cavity(ra):
+        return Cavity([sp, sp], ra, 0.71, storage=storage, use_torch_buffers=False, own_stream=True)
+
+    cavs = [cavity(ra) for ra in train_ra + held_ra]
+    hist = run_concurrent(cavs, steps, chunk)
+    inputs = np.concatenate([node_inputs(sp, ra) for ra in train_ra])
+    targets = np.concatenate([fields_star(c, uf) for c in cavs[:n_train]])
+    cold = [[(h[0], h[1]) for h in hh] for hh in hist[n_train:]]
+    for c in cavs:
+        c.close()
+    t_cold = time.perf_counter() - t0
+    if log:
+        log(f"warm-start study: cold solves done in {t_cold:.1f} s")
+    net = WarmStartMLP(MLPConfig(seed=seed))
+    losses = net.train(torch.tensor(inputs, device=net.device), torch.tensor(targets, device=net.device),
+                       steps=train_steps, batch=4096, log_every=max(1, train_steps // 4))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0 - t_cold
+    wcavs = [cavity(ra) for ra in held_ra]
+    for c, ra in zip(wcavs, held_ra):
+        predict_init(net, c, sp, ra, uf)
+    warm_hist = run_concurrent(wcavs, steps, chunk)
+    for c in wcavs:
+        c.close()
+    rows = []
+    for ra, ch, wh in zip(held_ra, cold, warm_hist):
+        wl = [(h[0], h[1]) for h in wh]
+        ref = ch[-1][1]
+        rows.append({"Ra": ra, "nu_hot_cold_end": ref, "nu_hot_warm_end": wl[-1][1],
+                     "rel_diff_end": abs(wl[-1][1] - ref) / abs(ref),
+                     "prediction_rel_err": abs(wl[0][1] - ref) / abs(ref),
+                     "cold_steps": steps_within(ch, ref), "warm_steps": steps_within(wl, ref)})
+    cs = [r["cold_steps"] for r in rows]
+    ws = [r["warm_steps"] for r in rows]
+    total_c = sum(cs) if None not in cs else None
+    total_w = sum(ws) if None not in ws else None
+    return {"workload": f"2-D cavity {n}^2 erf mesh (a=1.5), Pr 0.71, Ma 0.1, {storage} storage; "
+                        f"{n_train} training / {n_held} held-out Ra log-uniform in "
+                        f"[1e{lo:g}, 1e{hi:g}]",
+            "criterion": "steps until Nu_hot stays within 1e-3 of the cold run's final value "
+                         f"(records every {chunk} steps; {steps} steps per run)",
+            "train": {"samples": int(inputs.shape[0]), "steps": train_steps, "batch": 4096,
+                      "loss_first": losses[0][1], "loss_last": losses[-1][1]},
+            "held_out": rows, "cold_steps_total": total_c, "warm_steps_total": total_w,
+            "steps_ratio_warm_over_cold": (total_w / total_c) if total_c and total_w is not None
+            else None,
+            "max_rel_diff_end": max(r["rel_diff_end"] for r in rows),
+            "seconds": {"cold": round(t_cold, 1), "train": round(t_train, 1),
+                        "total": round(time.perf_counter() - t0, 1)}}

@@ -1,5 +1,7 @@
 """End-to-end validation of the GPU solver against the paper's printed
-steady-state benchmark (Table 2, Ra = 1e6, 257^2 error-function mesh).
+steady-state benchmarks: Table 2 (2-D, Ra = 1e6 on the 257^2 and Ra = 1e7
+on the 513^2 error-function meshes) and the 3-D table of Sec. 4 (Ra = 1e5,
+129^3 error-function mesh).
 Not parity: the relaxation rates of the paper are not printed (the readings
 here differ at second order), so the bars are a few tenths of a percent.
 The Reynolds number is compared in its root-mean-square reading: the
@@ -38,4 +40,52 @@ def test_table2_ra1e6_257(storage):
     assert abs(st["nu_vol"] / ref["nu_vol"] - 1) < 2e-3
     assert abs(st["nu_mid"] / ref["nu_mid"] - 1) < 2e-3
     assert abs(st["nu_hot"] / ref["nu_hot"] - 1) < 5e-3
+    assert abs(st["re_rms"] / ref["re"] - 1) < 1e-2
+
+
+def _steady(cav, chunk, cap):
+    """Runs until <Nu> changes by less than 1e-6 (relative) over one chunk."""
+    prev, steps = None, 0
+    while steps < cap:
+        cav.step(chunk)
+        steps += chunk
+        st = cav.stats()
+        if prev is not None and abs(st["nu_vol"] - prev) < 1e-6 * abs(prev):
+            break
+        prev = st["nu_vol"]
+    return st, steps
+
+
+def test_table2_ra1e7_513():
+    """2-D, Ra = 1e7, 513^2 erf mesh, from rest, FP32 storage with FP64
+    arithmetic, same bars as at Ra = 1e6."""
+    ref = json.load(open(os.path.join(HERE, "golden", "table2_ra1e7.json")))["rows"]["513"]
+    sp = pkg.islbm_mesh_spacing("erf", 513, 1.5)
+    sp = sp / sp[0]
+    cav = pkg.Cavity([sp, sp], 1e7, 0.71, storage="fp32sr")
+    st, steps = _steady(cav, 100_000, 6_000_000)
+    cav.close()
+    print(f"513^2 Ra 1e7 steps {steps}: " + " ".join(f"{k} {st[k]:.5f}" for k in
+                                             ("nu_vol", "nu_hot", "nu_mid", "re_rms")), flush=True)
+    assert abs(st["nu_vol"] / ref["nu_vol"] - 1) < 2e-3
+    assert abs(st["nu_mid"] / ref["nu_mid"] - 1) < 2e-3
+    assert abs(st["nu_hot"] / ref["nu_hot"] - 1) < 5e-3
+    assert abs(st["re_rms"] / ref["re"] - 1) < 1e-2
+
+
+def test_table4_ra1e5_129():
+    """3-D cubic cavity, Ra = 1e5, 129^3 erf mesh, from rest, FP32 storage
+    with FP64 arithmetic; the hot-wall Nusselt number is the average over the
+    whole wall.  Bars as in 2-D."""
+    ref = json.load(open(os.path.join(HERE, "golden", "table4_ra1e5.json")))["rows"]["129"]
+    sp = pkg.islbm_mesh_spacing("erf", 129, 1.5)
+    sp = sp / sp[0]
+    cav = pkg.Cavity([sp, sp, sp], 1e5, 0.71, storage="fp32sr")
+    st, steps = _steady(cav, 40_000, 800_000)
+    cav.close()
+    print(f"129^3 Ra 1e5 steps {steps}: " + " ".join(f"{k} {st[k]:.5f}" for k in
+                                              ("nu_vol", "nu_hot", "nu_cold", "re_rms")), flush=True)
+    assert abs(st["nu_vol"] / ref["nu_vol"] - 1) < 2e-3
+    assert abs(st["nu_hot"] / ref["nu_hot"] - 1) < 5e-3
+    assert abs(st["nu_cold"] / ref["nu_hot"] - 1) < 5e-3
     assert abs(st["re_rms"] / ref["re"] - 1) < 1e-2
