@@ -56,6 +56,22 @@ int islbm_gemm_bf16(int mode, int M, int N, int K, const void* A, int lda, const
                     const float* aux, int ldaux, int epilogue, float* workspace,
                     size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the TN
+ * product of islbm_gemm_bf16 (mode 2, epilogue 0: C[M][N] = sum_k A[k][m] B[k][n],
+ * A: K x M bf16 with leading dimension lda >= M, B: K x N bf16 with ldb >= N,
+ * C: M x N floats with ldc >= N), its split-K partials held in a fixed 8 MiB
+ * device array inside the library instead of a workspace argument; the
+ * result equals that of islbm_gemm_bf16 with a workspace, bit for bit.  It
+ * allocates nothing (the array's device address is looked up once per device
+ * on the first call).  Limit: 4 * M * N * ceil(K / 1024) bytes <= 8 MiB, else
+ * -1 (ISLBM_EINVAL) with nothing launched; -1 also for NULL pointers or
+ * non-positive sizes, -5 for a launch or symbol-lookup failure.  All calls on
+ * one GPU share that array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller. */
+int islbm_gemm_bf16_tn_noalloc(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
+                               float* C, int ldc, void* stream);
+
 /* Weighted mean-squared-error gradient: for i < n, j < m,
  * r = y[i][j] - t[i][j]; g[i][j] = 2 w_j r / n (FP32 into gf and bf16 into gb,
  * either may be NULL); loss_out[0] = sum_ij w_j r^2 / n (FP64, one value,

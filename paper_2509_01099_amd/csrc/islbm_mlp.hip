@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstddef>
+#include <mutex>
 
 #include "../../include/islbm_mlp.h"
 
@@ -240,6 +241,53 @@ static hipError_t gemm_launch(int M, int N, int K, const void* A, int lda, const
 }  // namespace islbm_mlp
 
 using namespace islbm_mlp;
+
+// ---------------------------------------------------------------------------
+// Allocation-free TN product: the split-K partials live in a file-scope device
+// array instead of a caller workspace.  Host code never passes the array's
+// name to a kernel: it takes the array's device address once per device with
+// hipGetSymbolAddress and passes that.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;  // 8 MiB per device
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
+
+static std::once_flag g_scratch_once[kMaxDevices];
+static float* g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of `scratch` on the current device (set up on the first call
+// per device), or nullptr on failure.
+static float* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? static_cast<float*>(ptr) : nullptr;
+  });
+  return g_scratch_ptr[dev];
+}
+
+extern "C" int islbm_gemm_bf16_tn_noalloc(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
+                                          float* C, int ldc, void* stream) {
+  if (!A || !B || !C || M <= 0 || N <= 0 || K <= 0 || lda < M || ldb < N || ldc < N) return -1;
+  const int splits = (K + KSPLIT - 1) / KSPLIT;
+  if ((size_t)4 * M * N * splits > kNoAllocScratchBytes) return -1;  // beyond the fixed scratch
+  float* ws = scratch_on_current_device();
+  if (!ws) return -5;
+  hipStream_t st = (hipStream_t)stream;
+  // every split writes its whole M x N slice before the fixed-order sum reads
+  // it, so nothing of an earlier call's contents is read
+  hipError_t e = gemm_launch<2, 0>(M, N, K, A, lda, B, ldb, nullptr, 0, nullptr, 0, nullptr, nullptr, 0, ws, splits,
+                                   KSPLIT, st);
+  if (e != hipSuccess) return -5;
+  hipLaunchKernelGGL(splitk_sum_kernel, dim3(grid_for((long long)M * N)), dim3(256), 0, st, ws, splits, M, N, C, ldc);
+  return status(hipGetLastError());
+}
 
 extern "C" int islbm_mlp_features_d(const float* p, int n, int d, const float* B, int F, void* out, int ldo,
                                     void* stream) {

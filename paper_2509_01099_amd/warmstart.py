@@ -36,8 +36,10 @@ def _lib():
         lib.islbm_mlp_gather.argtypes = [P, I, P, I, I, P, I, P]
         lib.islbm_f32_to_bf16.argtypes = [P, P, S, P]
         lib.islbm_mlp_adam.argtypes = [P, P, P, P, P, S, F, F, F, F, F, I, P]
+        lib.islbm_gemm_bf16_tn_noalloc.argtypes = [I, I, I, P, I, P, I, P, I, P]
         for n in ("islbm_mlp_features", "islbm_mlp_features_d", "islbm_gemm_bf16", "islbm_mlp_mse_grad", "islbm_mlp_colsum",
-                  "islbm_mlp_gather", "islbm_f32_to_bf16", "islbm_mlp_adam"):
+                  "islbm_mlp_gather", "islbm_f32_to_bf16", "islbm_mlp_adam",
+                  "islbm_gemm_bf16_tn_noalloc"):
             getattr(lib, n).restype = C.c_int
         lib._mlp_ready = True
     return lib
@@ -70,6 +72,12 @@ def islbm_gemm_bf16(mode, M, N, K, A, lda, Bm, ldb, Cf=None, ldc=0, Cb=None, ldc
     wsb = ws.numel() * ws.element_size() if ws is not None else 0
     _ok(_lib().islbm_gemm_bf16(mode, M, N, K, _p(A), lda, _p(Bm), ldb, _p(Cf), ldc, _p(Cb), ldcb,
                                _p(bias), _p(aux), ldaux, epilogue, _p(ws), wsb, stream), "gemm")
+
+
+def islbm_gemm_bf16_tn_noalloc(M, N, K, A, lda, Bm, ldb, Cf, ldc, stream=None) -> int:
+    """C = A^T B with split-K partials in the library's fixed device array;
+    returns the status (0, -1 beyond the array or bad arguments, -5)."""
+    return _lib().islbm_gemm_bf16_tn_noalloc(M, N, K, _p(A), lda, _p(Bm), ldb, _p(Cf), ldc, stream)
 
 
 def islbm_mlp_mse_grad(y, t, w, gf=None, gb=None, loss=None, stream=None):
