@@ -167,12 +167,12 @@ def copy_ceiling(nbytes: int = 1 << 30, reps: int = 20) -> dict:
 
 def warmstart_block() -> dict:
     """Learned warm start on a small 2-D cavity (129^2 erf mesh, FP64 storage):
-    16 training and 4 held-out Rayleigh numbers in [1e6, 4e7]; steps to a
+    16 training and 4 held-out Rayleigh numbers in [1e6, 1e7]; steps to a
     steady Nusselt number from the network's prediction against the cold
     start from rest (the metric's second half)."""
     from paper_2509_01099_amd import warmstart as W
 
-    return W.quick_study(n=129, n_train=16, n_held=4, steps=600_000, train_steps=4000, log=_log)
+    return W.quick_study(n=129, n_train=16, n_held=4, steps=600_000, train_steps=8000, log=_log)
 
 
 def traffic_entry(dig: str):
