@@ -75,6 +75,7 @@ def time_run(cav, steps: int, warmup: int):
     import torch
 
     cav.step(warmup)
+    cav.plan(steps)                     # captures the launch graphs; runs no step
     cav.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -90,6 +91,7 @@ def time_run_split(cav, steps: int, warmup: int):
     import torch
 
     cav.step(warmup)
+    cav.plan(steps)                     # captures the launch graphs; runs no step
     cav.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

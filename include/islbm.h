@@ -152,8 +152,23 @@ int islbm_create(islbm_ctx** out, int lattice, const int n[3],
 /* Enqueues nsteps fused time steps (nsteps >= 0; 0 changes nothing).  The
  * last one also writes the FP64 reduction partials used by islbm_nu_re.
  * Runs of at least 128 plain steps are replayed in batches of 64 through a
- * HIP graph that the context captures on first use.  Asynchronous. */
+ * HIP graph that the context captures on first use (one per buffer parity).
+ * The plain launches left after the batches (at least 4 of them) are
+ * replayed from a graph of their own once the same count recurs from the same
+ * buffer parity, or after islbm_plan_steps asked for it; the context keeps
+ * four such graphs (a fifth count replaces the oldest, after waiting for the
+ * stream).  Options.no_graph = 1 launches every step directly.  Results are
+ * bitwise the same either way.  Asynchronous. */
 int islbm_step(islbm_ctx* ctx, long long nsteps);
+
+/* Captures, without running anything, the HIP graphs that a following
+ * islbm_step(ctx, nsteps) from the current state would replay (the 64-step
+ * batch graph and the graph of the remaining plain launches), so that call
+ * issues only graph launches and the final, reducing launch.  Advances no
+ * time level.  nsteps >= 0; ISLBM_EINVAL on a null context or negative
+ * count, ISLBM_EDEVICE when a capture fails.  A no-op when options.no_graph
+ * is set. */
+int islbm_plan_steps(islbm_ctx* ctx, long long nsteps);
 
 /* Macroscopic fields at the current time level (pre-collision moments:
  * rho = sum f, u = (sum e f + F/2)/rho, T = sum g) into host arrays of

@@ -30,7 +30,8 @@ EXPORTS = ("islbm_default_options", "islbm_query_bytes", "islbm_mesh_spacing", "
            "islbm_init_fields_device", "islbm_info", "islbm_time", "islbm_set_time",
            "islbm_sync", "islbm_destroy", "islbm_strerror", "islbm_last_error",
            "islbm_time_steps", "islbm_state_bytes", "islbm_save_state", "islbm_load_state",
-           "islbm_steady_change", "islbm_time_steps_split", "islbm_copy_bytes")
+           "islbm_steady_change", "islbm_time_steps_split", "islbm_copy_bytes",
+           "islbm_plan_steps")
 
 
 class islbm_options(C.Structure):
@@ -84,6 +85,7 @@ def load() -> C.CDLL:
     lib.islbm_create.argtypes = [C.POINTER(P), C.c_int, C.POINTER(C.c_int), C.POINTER(_D),
                                  C.c_double, C.c_double, C.POINTER(islbm_options)]
     lib.islbm_step.argtypes = [P, C.c_longlong]
+    lib.islbm_plan_steps.argtypes = [P, C.c_longlong]
     lib.islbm_fields.argtypes = [P, _D, _D, _D, _D, _D]
     lib.islbm_fields_device.argtypes = [P, P, P, P, P, P]
     lib.islbm_nu_re.argtypes = [P, C.POINTER(islbm_stats)]
@@ -189,6 +191,12 @@ def islbm_time_steps_split(ctx, nsteps: int) -> tuple:
     _check(load().islbm_time_steps_split(ctx, int(nsteps), C.byref(tot), C.byref(plain),
                                          C.byref(red)), ctx)
     return tot.value, plain.value, red.value
+
+
+def islbm_plan_steps(ctx, nsteps: int) -> None:
+    """Captures the launch graphs a following islbm_step(ctx, nsteps) from the
+    current state replays; advances nothing."""
+    _check(load().islbm_plan_steps(ctx, int(nsteps)), ctx)
 
 
 def islbm_copy_bytes(dst_ptr: int, src_ptr: int, nbytes: int, stream=None) -> None:
@@ -341,6 +349,9 @@ class Cavity:
 
     def step(self, n: int) -> None:
         islbm_step(self.ctx, n)
+
+    def plan(self, n: int) -> None:
+        islbm_plan_steps(self.ctx, n)
 
     def time_steps(self, n: int) -> float:
         return islbm_time_steps(self.ctx, n)

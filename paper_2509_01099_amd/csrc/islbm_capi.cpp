@@ -49,8 +49,16 @@ struct islbm_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   long long t = 0;
   int no_graph = 0;
-  hipGraphExec_t graph = nullptr;
-  int graph_steps = 0;
+  hipGraphExec_t batch[2] = {nullptr, nullptr};  // 64 plain launches from buffer parity 0 / 1
+  // graphs of the plain launches left after the 64-step batches, keyed by
+  // launch count and the buffer parity they start from (round-robin slots)
+  struct Tail {
+    hipGraphExec_t exec = nullptr;
+    long long steps = 0;
+    int parity = 0;
+  } tail[4];
+  int tail_next = 0;
+  long long tail_last = -1;  // key of the previous remainder left ungraphed
   std::string err;
 };
 
@@ -175,7 +183,10 @@ static void release(islbm_ctx* c) {
   auto dfree = [](void* p) {
     if (p) (void)hipFree(p);
   };
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  for (auto& b : c->batch)
+    if (b) (void)hipGraphExecDestroy(b);
+  for (auto& t : c->tail)
+    if (t.exec) (void)hipGraphExecDestroy(t.exec);
   if (c->own_buf)
     for (auto& b : c->buf) dfree(b);
   for (auto& w : c->wtab) dfree(w);
@@ -521,16 +532,23 @@ static hipError_t one_step(islbm_ctx* c, bool reduce) {
 // Replays of an even batch of plain steps through one HIP graph (the batch
 // returns the state to the same buffer pair, so the graph is reusable).
 static constexpr int kGraphBatch = 64;
+// Remainders of at least this many plain launches are replayed from a graph
+// once the same remainder recurs (or islbm_plan_steps asked for it).
+static constexpr int kTailMin = 4;
 
-static hipError_t build_graph(islbm_ctx* c) {
+// Captures `count` plain launches starting from buffer parity `parity` into
+// an executable graph (nothing runs).
+static hipError_t capture_plain(islbm_ctx* c, long long count, int parity, hipGraphExec_t* out) {
+  *out = nullptr;
   hipStream_t cap;
   hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
   hipGraph_t g = nullptr;
+  const int rpar = c->s.rpar;
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    int cur = c->cur;
-    for (int i = 0; i < kGraphBatch && e == hipSuccess; ++i) {
+    int cur = parity;
+    for (long long i = 0; i < count && e == hipSuccess; ++i) {
       c->s.rpar = cur;
       e = islbm::launch_step(c->s, fbuf(c, cur), gbuf(c, cur), fbuf(c, cur ^ 1), gbuf(c, cur ^ 1), false,
                              c->partials, cap);
@@ -539,12 +557,49 @@ static hipError_t build_graph(islbm_ctx* c) {
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  c->s.rpar = rpar;
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
   (void)hipStreamDestroy(cap);
-  if (e == hipSuccess) c->graph_steps = c->cur;  // buffer parity the graph starts from
-  else c->graph = nullptr;
+  if (e != hipSuccess) *out = nullptr;
   return e;
+}
+
+// The batch graph for the current buffer parity, captured on first use.
+static hipGraphExec_t batch_graph(islbm_ctx* c, hipError_t* err) {
+  *err = hipSuccess;
+  hipGraphExec_t& g = c->batch[c->cur];
+  if (!g) *err = capture_plain(c, kGraphBatch, c->cur, &g);
+  return g;
+}
+
+static islbm_ctx::Tail* find_tail(islbm_ctx* c, long long count, int parity) {
+  for (auto& t : c->tail)
+    if (t.exec && t.steps == count && t.parity == parity) return &t;
+  return nullptr;
+}
+
+static hipError_t add_tail(islbm_ctx* c, long long count, int parity) {
+  islbm_ctx::Tail& t = c->tail[c->tail_next];
+  if (t.exec) {
+    hipError_t e = hipStreamSynchronize(c->stream);  // a replay of it may still be queued
+    if (e != hipSuccess) return e;
+    (void)hipGraphExecDestroy(t.exec);
+    t.exec = nullptr;
+  }
+  hipError_t e = capture_plain(c, count, parity, &t.exec);
+  if (e != hipSuccess) return e;
+  t.steps = count;
+  t.parity = parity;
+  c->tail_next = (c->tail_next + 1) % 4;
+  return hipSuccess;
+}
+
+// How a run of nsteps launches splits: batches of kGraphBatch plain launches
+// (when there are at least two batches' worth), then `rest` plain launches,
+// then the reducing one.
+static long long batches_of(const islbm_ctx* c, long long plain) {
+  return (!c->no_graph && plain >= 2 * kGraphBatch) ? plain / kGraphBatch : 0;
 }
 
 // mid (optional): an event recorded between the plain launches and the
@@ -552,21 +607,33 @@ static hipError_t build_graph(islbm_ctx* c) {
 static int enqueue_steps(islbm_ctx* c, long long nsteps, hipEvent_t mid = nullptr) {
   if (nsteps <= 0) return ISLBM_OK;
   long long plain = nsteps - 1;  // the last launch reduces
-  if (!c->no_graph && plain >= 2 * kGraphBatch) {
-    if (!c->graph || c->graph_steps != c->cur) {
-      if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-      }
-      if (build_graph(c) != hipSuccess) c->no_graph = 1;
-    }
-    if (c->graph) {
+  if (batches_of(c, plain) > 0) {
+    hipError_t ge;
+    hipGraphExec_t g = batch_graph(c, &ge);
+    if (ge != hipSuccess) c->no_graph = 1;
+    if (g) {
       while (plain >= kGraphBatch) {
-        hipError_t e = hipGraphLaunch(c->graph, c->stream);
+        hipError_t e = hipGraphLaunch(g, c->stream);
         if (e != hipSuccess) return hipfail(c, e, "hipGraphLaunch");
         c->t += kGraphBatch;
         plain -= kGraphBatch;
       }
+    }
+  }
+  if (!c->no_graph && plain >= kTailMin) {
+    const long long key = 2 * plain + c->cur;
+    islbm_ctx::Tail* t = find_tail(c, plain, c->cur);
+    if (!t && key == c->tail_last) {
+      if (add_tail(c, plain, c->cur) == hipSuccess) t = find_tail(c, plain, c->cur);
+      else c->no_graph = 1;
+    }
+    c->tail_last = key;
+    if (t) {
+      hipError_t e = hipGraphLaunch(t->exec, c->stream);
+      if (e != hipSuccess) return hipfail(c, e, "hipGraphLaunch");
+      c->t += plain;
+      if (plain & 1) c->cur ^= 1;
+      plain = 0;
     }
   }
   for (long long i = 0; i < plain; ++i) {
@@ -578,6 +645,24 @@ static int enqueue_steps(islbm_ctx* c, long long nsteps, hipEvent_t mid = nullpt
   if (e != hipSuccess) return hipfail(c, e, "step kernel (reducing)");
   c->partials_valid = true;
   c->partials_n = islbm::step_blocks(c->s);
+  return ISLBM_OK;
+}
+
+extern "C" int islbm_plan_steps(islbm_ctx* ctx, long long nsteps) {
+  if (!ctx || nsteps < 0) return ISLBM_EINVAL;
+  if (ctx->no_graph || nsteps == 0) return ISLBM_OK;
+  long long plain = nsteps - 1;
+  const long long nb = batches_of(ctx, plain);
+  if (nb > 0) {
+    hipError_t e;
+    (void)batch_graph(ctx, &e);
+    if (e != hipSuccess) return hipfail(ctx, e, "graph capture");
+    plain -= nb * kGraphBatch;
+  }
+  if (plain >= kTailMin && !find_tail(ctx, plain, ctx->cur)) {
+    hipError_t e = add_tail(ctx, plain, ctx->cur);
+    if (e != hipSuccess) return hipfail(ctx, e, "graph capture");
+  }
   return ISLBM_OK;
 }
 

@@ -574,20 +574,28 @@ __device__ __forceinline__ void pull_all(const L* lds, const NodeGeo<R>& q, cons
 }
 
 // ---------------------------------------------------------------------------
-// Reductions: per-thread FP64 accumulators, wave shuffles, one partial record
-// per workgroup.
+// Reductions: per-thread accumulators, wave reductions, one partial record
+// per workgroup (record slots: 0-7 and 12 FP64 sums, 8-10 maxima of |u*|,
+// 11 the count of non-finite nodes).
 // ---------------------------------------------------------------------------
+template <typename R>
 struct RedAcc {
-  double v[kRedSlots];
+  double v[kRedSlots];  // the sums (maxima and count slots unused here)
+  R umax[3];            // max |u_a| in lattice units, in the arithmetic type
+  unsigned bad;         // non-finite nodes
 };
 
-__device__ __forceinline__ void red_init(RedAcc& r) {
+template <typename R>
+__device__ __forceinline__ void red_init(RedAcc<R>& r) {
 #pragma unroll
   for (int i = 0; i < kRedSlots; ++i) r.v[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.umax[i] = R(0);
+  r.bad = 0u;
 }
 
 template <typename R>
-__device__ __forceinline__ void red_node(RedAcc& r, const KArgs<R>& a, const int* g, const Macro<R>& m) {
+__device__ __forceinline__ void red_node(RedAcc<R>& r, const KArgs<R>& a, const int* g, const Macro<R>& m) {
   const double* red = a.red;
   const double A = red[a.red_vol[1] + g[1]] * red[a.red_vol[2] + g[2]];
   const double W = red[a.red_vol[0] + g[0]] * A;
@@ -604,37 +612,82 @@ __device__ __forceinline__ void red_node(RedAcc& r, const KArgs<R>& a, const int
   r.v[5] += A * red[a.red_chot + g[0]] * Ts;
   r.v[6] += A * red[a.red_ccold + g[0]] * Ts;
   r.v[7] += A * (red[a.red_cmv + g[0]] * us * Ts + red[a.red_cmd + g[0]] * Ts);
-  r.v[8] = fmax(r.v[8], fabs(us));
-  r.v[9] = fmax(r.v[9], fabs(vs));
-  r.v[10] = fmax(r.v[10], fabs(ws));
+  // max |u*| = (max |u|) / u_f exactly: scaling by a positive constant and
+  // rounding are both monotonic
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.umax[i] = fmax(r.umax[i], fabs(m.u[i]));
   const bool bad = !(isfinite(rho) && isfinite(us) && isfinite(vs) && isfinite(ws) && isfinite(Ts));
-  r.v[11] += bad ? 1.0 : 0.0;
+  r.bad += bad ? 1u : 0u;
   r.v[12] += W * (us * us + vs * vs + ws * ws);
 }
 
-template <int NT>
-__device__ __forceinline__ void red_block(RedAcc& r, double* out) {
+// Cross-lane moves within rows of 16 lanes (DPP; no LDS traffic):
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+  return unsigned(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = dpp_u32<CTRL>(unsigned(b)), hi = dpp_u32<CTRL>(unsigned(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __uint_as_float(dpp_u32<CTRL>(__float_as_uint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp(unsigned v) {
+  return dpp_u32<CTRL>(v);
+}
+
+// Wave-wide sum or maximum in a fixed order, the result in every lane: the
+// four in-row levels by DPP moves, the two cross-row levels by shuffles.
+// Each level combines a lane's value with its partner's, and x + y == y + x
+// exactly, so the lanes of a pair hold the same value after every level.
+template <bool MAX, typename V>
+__device__ __forceinline__ V wave_reduce(V v) {
+  auto op = [](V x, V y) { return MAX ? V(fmax(x, y)) : V(x + y); };
+  v = op(v, dpp<kDppXor1>(v));
+  v = op(v, dpp<kDppXor2>(v));
+  v = op(v, dpp<kDppHalfMirror>(v));
+  v = op(v, dpp<kDppMirror>(v));
+  v = op(v, __shfl_xor(v, 16, 64));
+  v = op(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
+template <int NT, typename R>
+__device__ __forceinline__ void red_block(RedAcc<R>& r, double inv_uf, double* out) {
   constexpr int NW = NT / 64;
   __shared__ double sh[NW][kRedSlots];
+  double w[kRedSlots];
+  w[0] = wave_reduce<false>(r.v[0]);
+  w[1] = wave_reduce<false>(r.v[1]);
+  w[2] = wave_reduce<false>(r.v[2]);
+  w[3] = wave_reduce<false>(r.v[3]);
+  w[4] = wave_reduce<false>(r.v[4]);
+  w[12] = wave_reduce<false>(r.v[12]);
+  // slots 5-7 are non-zero only next to the walls and the mid-plane: waves
+  // with no such node skip them (a wave-uniform branch)
 #pragma unroll
-  for (int i = 0; i < kRedSlots; ++i) {
-    double v = r.v[i];
+  for (int i = 5; i <= 7; ++i)
+    w[i] = __ballot(r.v[i] != 0.0) ? wave_reduce<false>(r.v[i]) : 0.0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o = __shfl_xor(v, off, 64);
-      v = (i >= 8 && i <= 10) ? fmax(v, o) : v + o;
-    }
-    r.v[i] = v;
-  }
+  for (int i = 0; i < 3; ++i) w[8 + i] = double(wave_reduce<true>(r.umax[i])) * inv_uf;
+  w[11] = __ballot(r.bad != 0u) ? double(wave_reduce<false>(r.bad)) : 0.0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int i = 0; i < kRedSlots; ++i) sh[wid][i] = r.v[i];
+    for (int i = 0; i < kRedSlots; ++i) sh[wid][i] = w[i];
   __syncthreads();
   if (threadIdx.x < kRedSlots) {
     const int i = threadIdx.x;
     double v = sh[0][i];
-    for (int w = 1; w < NW; ++w) v = (i >= 8 && i <= 10) ? fmax(v, sh[w][i]) : v + sh[w][i];
+    for (int k = 1; k < NW; ++k) v = (i >= 8 && i <= 10) ? fmax(v, sh[k][i]) : v + sh[k][i];
     out[i] = v;
   }
 }
@@ -737,7 +790,7 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
   }(std::make_integer_sequence<int, SL::N>{});
   __syncthreads();
 
-  RedAcc acc;
+  RedAcc<R> acc;
   if constexpr (REDUCE) red_init(acc);
   char* fo = reinterpret_cast<char*>(fout) + (long long)R0 * a.rsf * SB;
   char* go = reinterpret_cast<char*>(gout) + (long long)R0 * a.rsg * SB;
@@ -774,13 +827,9 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
     Macro<R> m;
     if constexpr (COLLIDE) {
       collide<D>(d, g, a.k, m);
-      if constexpr (REDUCE) red_node(acc, a, q.g, m);
     } else {
-      if constexpr (REDUCE) {
-        // stream-only: the statistics describe the streamed (pre-collision) state
-        macro_post<D>(d, g, a.k, m);
-        red_node(acc, a, q.g, m);
-      }
+      // stream-only: the statistics describe the streamed (pre-collision) state
+      if constexpr (REDUCE) macro_post<D>(d, g, a.k, m);
     }
     const long long mrow = (long long)q.g[2] * a.n[1] + q.g[1];
     // rounding bits keyed by the node (its index in a row-pitched mesh)
@@ -795,10 +844,13 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
 #pragma unroll
     for (int i = 0; i < LG::Q; ++i)
       store_pop<S, NTS>(reinterpret_cast<S*>(atb(go, cg + unsigned(i) * prow)), g[i], h0, 32 + i);
+    // after the stores, so that the FP64 statistics do not hold registers
+    // while the populations are still live
+    if constexpr (REDUCE) red_node(acc, a, q.g, m);
   }
   if constexpr (REDUCE) {
     const int lb = blockIdx.x;
-    red_block<T::NT>(acc, a.partials + (long long)lb * kRedSlots);
+    red_block<T::NT>(acc, a.inv_uf, a.partials + (long long)lb * kRedSlots);
   }
 }
 
@@ -1050,7 +1102,7 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
   commit_class<M, false, R>(lds, regs, 0, slots);
   __syncthreads();
 
-  RedAcc acc;
+  RedAcc<R> acc;
   if constexpr (REDUCE) red_init(acc);
 
 #pragma unroll 1
@@ -1079,7 +1131,6 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
       mpull_all<M>(lds, q, a, d, g, slots);
       Macro<R> m;
       collide<3>(d, g, a.k, m);
-      if constexpr (REDUCE) red_node(acc, a, q.g, m);
       const long long hc = ((long long)z * a.n[1] + gy0) * a.pitch + gx0;
       const unsigned h0 = Store<S>::kDither ? mix32(unsigned(hc) ^ dkey) : 0u;
       const long long cf = (long long)z * zsf + cxyf, cg = (long long)z * zsg + cxyg;
@@ -1087,6 +1138,7 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
       for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(fout + (long long)i * a.ps + cf, d[i], h0, i);
 #pragma unroll
       for (int i = 0; i < LG::Q; ++i) store_pop<S, NTS>(gout + (long long)i * a.ps + cg, g[i], h0, 32 + i);
+      if constexpr (REDUCE) red_node(acc, a, q.g, m);
     }
     __syncthreads();
     if (more) commit_class<M, false, R>(lds, regs, 0, slots);
@@ -1095,7 +1147,7 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
     rg = ng;
     __syncthreads();
   }
-  if constexpr (REDUCE) red_block<M::NT>(acc, a.partials + (long long)blockIdx.x * kRedSlots);
+  if constexpr (REDUCE) red_block<M::NT>(acc, a.inv_uf, a.partials + (long long)blockIdx.x * kRedSlots);
 }
 
 // Tile shapes per lattice, arithmetic width and working-set class (TX x TY x
@@ -1576,7 +1628,7 @@ __global__ void __launch_bounds__(256) reduce_state_kernel(const S* __restrict__
                                                            KArgs<typename Store<S>::R> a) {
   using R = typename Store<S>::R;
   const long long nn = (long long)a.n[0] * a.n[1] * a.n[2];
-  RedAcc acc;
+  RedAcc<R> acc;
   red_init(acc);
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
        k += (long long)gridDim.x * blockDim.x) {
@@ -1590,7 +1642,7 @@ __global__ void __launch_bounds__(256) reduce_state_kernel(const S* __restrict__
     gi[2] = (int)(k / ((long long)a.n[0] * a.n[1]));
     red_node(acc, a, gi, m);
   }
-  red_block<256>(acc, a.partials + (long long)blockIdx.x * kRedSlots);
+  red_block<256>(acc, a.inv_uf, a.partials + (long long)blockIdx.x * kRedSlots);
 }
 
 int reduce_state_blocks(const DevState& s) {
