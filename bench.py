@@ -453,12 +453,17 @@ def converge_stats(cav, max_steps: int, tol: float = 1e-8, check: int = 20000, l
 
 
 def convergence_3d(Ra: float = 1e5, sizes=(129, 181, 257), storage: str = "fp32sr",
-                   max_steps=(600_000, 600_000, 600_000)) -> dict:
+                   max_steps=(600_000, 600_000, 600_000), init_file: str = "",
+                   save_file: str = "", prior: dict = None) -> dict:
     """Grid convergence of the steady 3-D cavity on the erf meshes of the
     Sec. 4 table (a = 1.5): the coarsest mesh starts at rest, each finer mesh
     from the previous mesh's steady fields (trilinear interpolation), each is
     run until its integrals are steady; Richardson extrapolation and GCI with
-    the table's refinement ratio r = 1.41."""
+    the table's refinement ratio r = 1.41 over the last three meshes.
+    A study can be split over several processes: `save_file` keeps the last
+    mesh's steady fields (FP16, an initial guess only), `init_file` starts the
+    first mesh from them, and `prior` (an earlier output) supplies the runs of
+    the coarser meshes."""
     import numpy as np
     from scipy.interpolate import RegularGridInterpolator
 
@@ -467,6 +472,12 @@ def convergence_3d(Ra: float = 1e5, sizes=(129, 181, 257), storage: str = "fp32s
 
     keys = ("nu_vol", "nu_hot", "nu_cold", "re_rms")
     vals, runs, prev = {}, [], None
+    for r in (prior or {}).get("runs", []):
+        runs.append(r)
+        vals[r["n"]] = {k: r[k] for k in keys}
+    if init_file:
+        with np.load(init_file, allow_pickle=False) as z:
+            prev = (z["c"], {k: z[k].astype(np.float64) for k in ("ux", "uy", "uz", "T")})
     for n, cap in zip(sizes, max_steps):
         sp = W.mesh_spacing("erf", n, 1.5)
         cav = pkg.Cavity([sp, sp, sp], Ra, PR, storage=storage)
@@ -499,14 +510,19 @@ def convergence_3d(Ra: float = 1e5, sizes=(129, 181, 257), storage: str = "fp32s
         runs.append(row)
         _log(f"{n}^3: {row}")
         cav.close()
+    if save_file and prev is not None:
+        np.savez(save_file, c=prev[0], **{k: v.astype(np.float16) for k, v in prev[1].items()})
     out = {"workload": f"3-D cavity Ra={Ra:g} Pr=0.71, erf meshes a=1.5, {storage}, coarsest "
                        "from rest, each finer mesh from the previous steady fields",
            "runs": runs}
-    if len(sizes) == 3:
+    done = [r["n"] for r in runs]
+    if len(done) >= 3:
+        last = done[-3:]
+        out["richardson_meshes"] = last
         out["richardson"] = {}
         for k in keys:
             try:
-                p, finf, gci = richardson(*(vals[n][k] for n in sizes), 1.41)
+                p, finf, gci = richardson(*(vals[n][k] for n in last), 1.41)
             except (ValueError, ZeroDivisionError):     # not monotone in N, or equal
                 p = finf = gci = None
             out["richardson"][k] = {"p": p, "extrapolated": finf, "gci_fine_pct": gci}
@@ -847,6 +863,14 @@ def main() -> int:
                          "3-D table (1e5: 129/181/257), FP32 storage with FP64 arithmetic")
     ap.add_argument("--c3-sizes", default="",
                     help="comma-separated mesh sizes of --convergence3d (default: the table's)")
+    ap.add_argument("--c3-save", default="", metavar="NPZ",
+                    help="--convergence3d: save the last mesh's steady fields (FP16) here")
+    ap.add_argument("--c3-init", default="", metavar="NPZ",
+                    help="--convergence3d: start the first mesh from fields saved by --c3-save")
+    ap.add_argument("--c3-caps", default="",
+                    help="--convergence3d: comma-separated step caps per mesh")
+    ap.add_argument("--c3-prior", default="", metavar="JSON",
+                    help="--convergence3d: an earlier output whose runs precede these meshes")
     ap.add_argument("--validation3d", action="store_true",
                     help="steady 3-D cavity (129^3 erf, Ra 1e5, FP64) against the paper's table")
     ap.add_argument("--profile-mesh", choices=sorted(PROFILE_MESHES), default="2d",
@@ -875,8 +899,15 @@ def main() -> int:
     if args.convergence3d:
         sizes = tuple(int(v) for v in args.c3_sizes.split(",")) if args.c3_sizes else (
             (129, 181, 257) if args.convergence3d < 5e5 else (181, 257, 361))
-        caps = (600_000, 500_000, 450_000)[:len(sizes)]
-        print(json.dumps(convergence_3d(args.convergence3d, sizes, max_steps=caps)))
+        caps = (tuple(int(v) for v in args.c3_caps.split(",")) if args.c3_caps
+                else (600_000, 500_000, 450_000)[:len(sizes)])
+        prior = None
+        if args.c3_prior:
+            with open(args.c3_prior) as f:
+                prior = json.loads(f.read().strip().splitlines()[-1])
+        print(json.dumps(convergence_3d(args.convergence3d, sizes, max_steps=caps,
+                                        init_file=args.c3_init, save_file=args.c3_save,
+                                        prior=prior)))
         return 0
     if args.throughput:
         print(json.dumps(throughput_table()))

@@ -1240,13 +1240,14 @@ static hipError_t dispatch_step(const DevState& s, const void* fin, const void* 
                 : launch_step_t<D, S, LARGE, false, false, false>(s, fin, gin, fout, gout, partials, st);
 }
 
-// Uniform 3-D meshes with collision and FP32 arithmetic (FP32 / FP16 / BF16
-// storage) use the z-marching kernel.
+// Uniform 3-D meshes with collision and FP32 storage use the z-marching
+// kernel.  FP16 / BF16 storage keeps the tile kernel, whose 2-byte tiles
+// (paired staging, half-precision LDS for FP16) outrun the marching kernel's
+// FP32 plane ring for these types.
 using March3 = March<32, 8, 32>;
 
 static bool use_march(const DevState& s) {
-  const bool fp32_arith = s.storage == 0 || s.storage == 2 || s.storage == 3;
-  return s.dim == 3 && fp32_arith && s.uniform != 0 && s.collide != 0;
+  return s.dim == 3 && s.storage == 0 && s.uniform != 0 && s.collide != 0;
 }
 
 static int march_grid(const DevState& s, int* tiles) {

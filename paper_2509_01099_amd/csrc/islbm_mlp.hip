@@ -32,6 +32,47 @@ __device__ __forceinline__ float dsilu(float z) {
 
 __device__ __forceinline__ __bf16 ld_bf(const __bf16* p) { return *p; }
 
+// Staging of one BK-slice of an operand into a [64][LDK] LDS tile, rows r0..
+// r0+63 of `rows` and columns k0..k0+BK-1 (below kend).  Each thread moves 8
+// consecutive elements with one 16-byte load when they lie inside the
+// operand and the address is 16-byte aligned, else element by element (edges,
+// odd leading dimensions); elements outside the operand are zero.
+//   stage_k: the operand is rows x K with K contiguous (row r at src + r*ld);
+//            a thread covers k..k+7 of one row, stored as one 16-byte row
+//            segment of the tile.
+//   stage_t: the operand is K x rows with rows contiguous (k at src + k*ld);
+//            a thread covers rows r..r+7 of one k, stored transposed.
+__device__ __forceinline__ void stage_k(const __bf16* __restrict__ src, int ld, int rows, int r0, int k0,
+                                        int kend, __bf16 (*dst)[LDK]) {
+  static_assert(BM == 64 && BN == 64 && BK == 32, "one 8-element unit per thread");
+  const int r = threadIdx.x >> 2, kk = (threadIdx.x & 3) * 8;
+  const int gr = r0 + r, gk = k0 + kk;
+  const __bf16* p = src + (long long)gr * ld + gk;
+  if (gr < rows && gk + 8 <= kend && (reinterpret_cast<size_t>(p) & 15) == 0) {
+    *reinterpret_cast<bf16x8*>(&dst[r][kk]) = *reinterpret_cast<const bf16x8*>(p);
+  } else {
+    const __bf16 zero = __bf16(0.0f);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dst[r][kk + i] = (gr < rows && gk + i < kend) ? ld_bf(p + i) : zero;
+  }
+}
+
+__device__ __forceinline__ void stage_t(const __bf16* __restrict__ src, int ld, int rows, int r0, int k0,
+                                        int kend, __bf16 (*dst)[LDK]) {
+  const int kk = threadIdx.x >> 3, r = (threadIdx.x & 7) * 8;
+  const int gk = k0 + kk, gr = r0 + r;
+  const __bf16* p = src + (long long)gk * ld + gr;
+  if (gk < kend && gr + 8 <= rows && (reinterpret_cast<size_t>(p) & 15) == 0) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(p);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dst[r + i][kk] = v[i];
+  } else {
+    const __bf16 zero = __bf16(0.0f);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dst[r + i][kk] = (gk < kend && gr + i < rows) ? ld_bf(p + i) : zero;
+  }
+}
+
 template <int MODE, int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, const __bf16* __restrict__ A, int lda,
                                                    const __bf16* __restrict__ B, int ldb, float* __restrict__ C,
@@ -46,46 +87,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, const __
   const int kend = min(K, kbeg + kchunk);
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const __bf16 zero = __bf16(0.0f);
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
 
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // A slice -> As[m][k]
-#pragma unroll
-    for (int r = 0; r < (BM * BK) / 256; ++r) {
-      const int e = tid + r * 256;
-      int mm, kk;
-      if constexpr (MODE == 2) {  // A is K x M (M contiguous)
-        kk = e / BM;
-        mm = e % BM;
-      } else {                    // A is M x K (K contiguous)
-        mm = e / BK;
-        kk = e % BK;
-      }
-      const int gm = m0 + mm, gk = k0 + kk;
-      __bf16 v = zero;
-      if (gm < M && gk < kend) v = MODE == 2 ? ld_bf(A + (long long)gk * lda + gm) : ld_bf(A + (long long)gm * lda + gk);
-      As[mm][kk] = v;
-    }
-    // B slice -> Bs[n][k]
-#pragma unroll
-    for (int r = 0; r < (BN * BK) / 256; ++r) {
-      const int e = tid + r * 256;
-      int nn, kk;
-      if constexpr (MODE == 0) {  // B is N x K (K contiguous)
-        nn = e / BK;
-        kk = e % BK;
-      } else {                    // B is K x N (N contiguous)
-        kk = e / BN;
-        nn = e % BN;
-      }
-      const int gn = n0 + nn, gk = k0 + kk;
-      __bf16 v = zero;
-      if (gn < N && gk < kend) v = MODE == 0 ? ld_bf(B + (long long)gn * ldb + gk) : ld_bf(B + (long long)gk * ldb + gn);
-      Bs[nn][kk] = v;
-    }
+    // A slice -> As[m][k], B slice -> Bs[n][k]
+    if constexpr (MODE == 2) stage_t(A, lda, M, m0, k0, kend, As);  // A is K x M (M contiguous)
+    else stage_k(A, lda, M, m0, k0, kend, As);                      // A is M x K (K contiguous)
+    if constexpr (MODE == 0) stage_k(B, ldb, N, n0, k0, kend, Bs);  // B is N x K (K contiguous)
+    else stage_t(B, ldb, N, n0, k0, kend, Bs);                      // B is K x N (N contiguous)
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {

@@ -66,6 +66,36 @@ def test_convergence_3d_host_logic(monkeypatch):
     assert abs(p - _Cavity.P) < 0.3, p
 
 
+def test_convergence_3d_split_over_processes(monkeypatch, tmp_path):
+    """The same study run as two parts (the coarse meshes saving their last
+    steady fields, the finest mesh starting from them with the earlier runs
+    as prior) gives the same runs and Richardson values as one run."""
+    import json
+
+    monkeypatch.setattr(pkg, "Cavity", lambda *a, **k: _Cavity(*a, **k))
+    sizes = (9, 13, 19)
+    whole = bench.convergence_3d(1e5, sizes, max_steps=(10 ** 6,) * 3)
+    npz = str(tmp_path / "f.npz")
+    first = bench.convergence_3d(1e5, sizes[:2], max_steps=(10 ** 6,) * 2, save_file=npz)
+    assert "richardson" not in first
+    prior = json.loads(json.dumps(first))
+    made = []
+
+    def factory(*a, **k):
+        made.append(_Cavity(*a, **k))
+        return made[-1]
+
+    monkeypatch.setattr(pkg, "Cavity", factory)
+    second = bench.convergence_3d(1e5, sizes[2:], max_steps=(10 ** 6,), init_file=npz, prior=prior)
+    # the finest mesh starts from the saved (FP16) coarse fields
+    assert made[0].inits is not None and made[0].inits[3].shape == (19, 19, 19)
+    assert abs(made[0].inits[3][0, 0, 0] - made[0].inits[3][0, 0, -1] - 1.0) < 0.2
+    assert [r["n"] for r in second["runs"]] == list(sizes)
+    assert second["richardson_meshes"] == list(sizes)
+    for k in ("nu_vol", "re_rms"):
+        assert abs(second["richardson"][k]["p"] - whole["richardson"][k]["p"]) < 1e-12
+
+
 def test_wctpdt_rows_scale_with_free_fall_time(monkeypatch):
     """WCTpDT = time per step x H_lu / u_f; the erf row carries the paper's
     figure and the ratios to the uniform mesh of the same node count."""
