@@ -421,7 +421,10 @@ TABLE_3D = {(1e5, 129): (4.3406, 4.3624, 4.3624, 39.4521),
             (1e5, 257): (4.3346, 4.3457, 4.3457, 39.3500),
             (1e6, 181): (8.6601, 8.6931, 8.6931, 97.4828),
             (1e6, 257): (8.6441, 8.6669, 8.6668, 97.0075),
-            (1e6, 361): (8.6379, 8.6540, 8.6540, 96.8464)}
+            (1e6, 361): (8.6379, 8.6540, 8.6540, 96.8464),
+            (1e7, 181): (16.5341, 16.6161, 16.6158, 237.3925),
+            (1e7, 257): (16.4179, 16.4681, 16.4680, 230.7625),
+            (1e7, 361): (16.3670, 16.4001, 16.4001, 228.4148)}
 
 
 def converge_stats(cav, max_steps: int, tol: float = 1e-8, check: int = 20000, lag: int = 2,

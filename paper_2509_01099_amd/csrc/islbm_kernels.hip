@@ -1150,6 +1150,297 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
   if constexpr (REDUCE) red_block<M::NT>(acc, a.inv_uf, a.partials + (long long)blockIdx.x * kRedSlots);
 }
 
+// ---------------------------------------------------------------------------
+// 3-D marching variant for stretched meshes (FP32 storage): the column and
+// plane ring of march3d_kernel, with the interpolated pulls of step_kernel.
+// The ring already holds the three stencil planes zb .. zb + 2 of plane z
+// (zb = clamp(z - 1, 0, nz - 3)), so z halos are read once per column.  The
+// planes are staged with direct global -> LDS loads (lane l of a wave writes
+// the wave's LDS base + 4 l), which need no staging registers: after the
+// pulls of plane z (and a barrier) the next plane's loads are issued into the
+// freed slots and land while plane z collides and is stored.  Measured on
+// 256^3 / 384^3 tanh meshes: 20.6k / 22.1k MLUPS against 20.6k / 20.2k for
+// step_kernel's 32 x 4 x 4 tiles.
+// ---------------------------------------------------------------------------
+// A workgroup-uniform plane base made opaque to the optimiser (kept in
+// scalar registers): otherwise it splits base + z * stride + offset and
+// hoists base + offset out of the z loop as one 64-bit vector address per
+// population and load unit, far more registers than the march can hold.
+// (The value must be the same in every lane: it is read from the first
+// active one.)
+template <typename P>
+__device__ __forceinline__ P opaque_base(P p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
+  return reinterpret_cast<P>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+typedef __attribute__((address_space(4))) const float CFloat;  // constant (scalar-cache) memory
+
+struct IGeo {
+  int g[3];
+  int own[2];       // own node in an unshifted x/y frame
+  int ownh[2];      // own node in a shifted x/y frame
+  int base[2];      // clamped x/y stencil base in the shifted frame
+  float wp[3][3];   // weights, direction +1, per axis (z: of the current plane)
+  float wm[3][3];   // weights, direction -1
+  int ring[3];      // ring slots of the stencil planes zb, zb + 1, zb + 2
+  int ringown;      // ring slot of plane z
+};
+
+template <class M, int s>
+__device__ __forceinline__ float ipull_slot(const float* lds, const IGeo& q) {
+  using SL = Slots<3, typename M::T>;
+  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
+  constexpr int W = SL::ext(s, 0), P = MStage<M>::plane(s);
+  const int ix = ex ? q.base[0] : q.own[0];
+  const int iy = ey ? q.base[1] : q.own[1];
+  const float* Pxy = lds + SL::off(s) + ix + iy * W;
+  const float* wx = ex > 0 ? q.wp[0] : q.wm[0];
+  const float* wy = ey > 0 ? q.wp[1] : q.wm[1];
+  const float* wz = ez > 0 ? q.wp[2] : q.wm[2];
+  constexpr int nsh = (ex != 0) + (ey != 0) + (ez != 0);
+  if constexpr (nsh == 1 && ez == 0) {
+    constexpr int st = ex ? 1 : W;
+    const float* w = ex ? wx : wy;
+    return w[0] * Pxy[0] + w[1] * Pxy[st] + w[2] * Pxy[2 * st];
+  } else if constexpr (nsh == 1) {
+    return wz[0] * Pxy[q.ring[0] * P] + wz[1] * Pxy[q.ring[1] * P] + wz[2] * Pxy[q.ring[2] * P];
+  } else if constexpr (ez == 0) {
+    // x and y: inner axis x, outer y (as in step_kernel)
+    float acc = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float* Pb = Pxy + b * W;
+      const float v = wx[0] * Pb[0] + wx[1] * Pb[1] + wx[2] * Pb[2];
+      acc = b == 0 ? wy[0] * v : acc + wy[b] * v;
+    }
+    return acc;
+  } else {
+    // x or y with z: the in-plane axis first, then z across the ring
+    constexpr int s1 = ex ? 1 : W;
+    const float* w1 = ex ? wx : wy;
+    float acc = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float* Pb = Pxy + q.ring[b] * P;
+      const float v = w1[0] * Pb[0] + w1[1] * Pb[s1] + w1[2] * Pb[2 * s1];
+      acc = b == 0 ? wz[0] * v : acc + wz[b] * v;
+    }
+    return acc;
+  }
+}
+
+template <class M, int s>
+__device__ __forceinline__ void iwall_slot(const float* lds, const IGeo& q, const KArgs<float>& a, float& val) {
+  using SL = Slots<3, typename M::T>;
+  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
+  const bool wall = (ex == 1 && q.g[0] == 0) || (ex == -1 && q.g[0] == a.n[0] - 1) ||
+                    (ey == 1 && q.g[1] == 0) || (ey == -1 && q.g[1] == a.n[1] - 1) ||
+                    (ez == 1 && q.g[2] == 0) || (ez == -1 && q.g[2] == a.n[2] - 1);
+  if (!wall) return;
+  constexpr int so = SL::opps(s);
+  constexpr int W = SL::ext(so, 0), P = MStage<M>::plane(so);
+  const int ix = ex ? q.ownh[0] : q.own[0];
+  const int iy = ey ? q.ownh[1] : q.own[1];
+  const int iz = ez ? q.ringown : 0;
+  const float back = lds[SL::off(so) + ix + iy * W + iz * P];
+  if constexpr (SL::isg(s) && ex != 0) {
+    const float Tw = (ex == 1) ? a.Thot : a.Tcold;
+    val = -back + a.omega * Tw;
+  } else {
+    val = back;
+  }
+}
+
+template <class M, int... SS>
+__device__ __forceinline__ void ipull_all(const float* lds, const IGeo& q, const KArgs<float>& a, float* d,
+                                          float* g, std::integer_sequence<int, SS...>) {
+  using SL = Slots<3, typename M::T>;
+  ((SL::isg(SS) ? (g[SL::pop(SS)] = ipull_slot<M, SS>(lds, q)) : (d[SL::pop(SS)] = ipull_slot<M, SS>(lds, q))),
+   ...);
+  const bool edge = q.g[0] == 0 || q.g[0] == a.n[0] - 1 || q.g[1] == 0 || q.g[1] == a.n[1] - 1 ||
+                    q.g[2] == 0 || q.g[2] == a.n[2] - 1;
+  if (edge) (iwall_slot<M, SS>(lds, q, a, SL::isg(SS) ? g[SL::pop(SS)] : d[SL::pop(SS)]), ...);
+}
+
+// Direct global -> LDS staging of one slot's plane gz into ring slot `ring`
+// (slots without a z component have one plane).  Lanes past the plane box
+// stay idle; a wave's 64 lanes write 64 consecutive LDS entries.
+template <class M, int s>
+__device__ __forceinline__ void dma_plane(float* lds, const float* __restrict__ fin, const float* __restrict__ gin,
+                                          const unsigned* offf, const unsigned* offg, const KArgs<float>& a,
+                                          int gz, int ring) {
+  using SL = Slots<3, typename M::T>;
+  using MS = MStage<M>;
+  using MSH = MShapes<M>;
+  constexpr int m = MSH::of(s), V = MS::plane(s);
+  const bool g = SL::isg(s);
+  const long long rs = g ? a.rsg : a.rsf;
+  const char* base = opaque_base(reinterpret_cast<const char*>((g ? gin : fin) + (long long)SL::pop(s) * a.ps +
+                                                               (long long)gz * a.n[1] * rs));
+  const unsigned* off = (g ? offg : offf) + MSH::ooff(m);
+  float* dst = lds + SL::off(s) + (SL::e(s, 2) != 0 ? ring * V : 0) + (threadIdx.x & ~63);
+#pragma unroll
+  for (int k = 0; k < MS::iters(s); ++k) {
+    const int idx = threadIdx.x + k * M::NT;
+    if (V % M::NT == 0 || k + 1 < MS::iters(s) || idx < V)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(atb(base, off[k])), dst + k * M::NT, 4, 0,
+                                       0);
+  }
+}
+
+template <class M, bool ZC, int... SS>
+__device__ __forceinline__ void dma_class(float* lds, const float* fin, const float* gin, const unsigned* offf,
+                                          const unsigned* offg, const KArgs<float>& a, int gz, int ring,
+                                          std::integer_sequence<int, SS...>) {
+  using SL = Slots<3, typename M::T>;
+  ([&] {
+    if constexpr ((SL::e(SS, 2) != 0) == ZC) dma_plane<M, SS>(lds, fin, gin, offf, offg, a, gz, ring);
+  }(), ...);
+}
+
+// wait for this thread's direct-to-LDS loads (vmcnt(0)); the barrier that
+// follows makes every wave's loads visible
+__device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <class M, bool REDUCE, bool NTS>
+__global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict__ fin, const float* __restrict__ gin,
+                                                         float* __restrict__ fout, float* __restrict__ gout,
+                                                         KArgs<float> a) {
+  using S = float;
+  using R = float;
+  using SL = Slots<3, typename M::T>;
+  using LF = typename SL::LF;
+  using LG = typename SL::LG;
+  __shared__ float lds[SL::total];
+  constexpr auto slots = std::make_integer_sequence<int, SL::N>{};
+
+  // column and z segment of this workgroup (XCD-aware numbering as in step_kernel)
+  const int b = blockIdx.x;
+  const int xcd = b & 7, loc = b >> 3;
+  const int per = a.nblocks >> 3, rem = a.nblocks & 7;
+  const int lb = xcd * per + (xcd < rem ? xcd : rem) + loc;
+  const int cols = a.tiles[0] * a.tiles[1];
+  const int col = lb % cols, seg = lb / cols;
+  TileOrigin o;
+  o.t0[0] = (col % a.tiles[0]) * M::TX;
+  o.t0[1] = (col / a.tiles[0]) * M::TY;
+  o.t0[2] = 0;
+  o.lo[0] = clampi(o.t0[0] - 1, 0, a.n[0] - 3);
+  o.lo[1] = clampi(o.t0[1] - 1, 0, a.n[1] - 3);
+  o.lo[2] = 0;
+  const int nz = a.n[2];
+  const int z0 = seg * M::ZS;
+  const int z1 = min(nz, z0 + M::ZS);
+
+  IGeo q;
+  const int lx = threadIdx.x % M::TX, ly = threadIdx.x / M::TX;
+  q.g[0] = o.t0[0] + lx;
+  q.g[1] = o.t0[1] + ly;
+  q.own[0] = lx;
+  q.own[1] = ly;
+  q.ownh[0] = q.g[0] - o.lo[0];
+  q.ownh[1] = q.g[1] - o.lo[1];
+  const bool in = q.g[0] < a.n[0] && q.g[1] < a.n[1];
+  if (in) {
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+      q.base[ax] = clampi(q.g[ax] - 1, 0, a.n[ax] - 3) - o.lo[ax];
+      load_weights(a.wtab[ax], a.n[ax], q.g[ax], q.wp[ax], q.wm[ax]);
+    }
+  }
+  // every global access is a workgroup-uniform base (plane z of one
+  // population, in scalar registers) plus the thread's 32-bit in-plane byte
+  // offset, so no per-population 64-bit address stays live across the march
+  const unsigned gy0 = in ? unsigned(q.g[1]) : 0u, gx0 = in ? unsigned(q.g[0]) : 0u;
+  const unsigned cxyf = (__umul24(gy0, unsigned(a.rsf)) + gx0) * 4u, cxyg = (__umul24(gy0, unsigned(a.rsg)) + gx0) * 4u;
+  const long long zsf = (long long)a.n[1] * a.rsf * 4, zsg = (long long)a.n[1] * a.rsg * 4;
+  const long long ps4 = (long long)a.ps * 4;
+  const char* const fi = reinterpret_cast<const char*>(fin);
+  const char* const gi = reinterpret_cast<const char*>(gin);
+  char* const fo = reinterpret_cast<char*>(fout);
+  char* const go = reinterpret_cast<char*>(gout);
+
+  // in-plane staging offsets (once), then the prologue: the three stencil
+  // planes of z0 and the x/y planes of z0
+  unsigned offf[MShapes<M>::total], offg[MShapes<M>::total];
+  mplan<M, S, R>(offf, offg, a, o);
+  const int zb0 = clampi(z0 - 1, 0, nz - 3);
+#pragma unroll 1
+  for (int p = 0; p < 3; ++p) dma_class<M, true>(lds, fin, gin, offf, offg, a, zb0 + p, (zb0 + p) % 3, slots);
+  dma_class<M, false>(lds, fin, gin, offf, offg, a, z0, 0, slots);
+  R rf = *reinterpret_cast<const float*>(atb(opaque_base(fi + z0 * zsf), cxyf));
+  R rg = *reinterpret_cast<const float*>(atb(opaque_base(gi + z0 * zsg), cxyg));
+  dma_wait();
+  __syncthreads();
+
+  RedAcc<R> acc;
+  if constexpr (REDUCE) red_init(acc);
+
+#pragma unroll 1
+  for (int z = z0; z < z1; ++z) {
+    const bool more = z + 1 < z1;
+    const int zb = clampi(z - 1, 0, nz - 3);
+    const int zbn = clampi(z, 0, nz - 3);
+    const bool newz = more && zbn > zb;
+    R d[LF::Q], g[LG::Q];
+    // z weights of the plane: uniform, read through the scalar cache (a
+    // vector load here would make its wait also wait for the previous
+    // plane's stores, which complete in order with it)
+    {
+      const CFloat* wz = (const CFloat*)(opaque_base(a.wtab[2]));  // 4 floats per node and direction
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        q.wp[2][i] = wz[4 * z + i];
+        q.wm[2][i] = wz[4 * (nz + z) + i];
+      }
+    }
+    if (in) {
+      q.g[2] = z;
+      q.ringown = z % 3;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) q.ring[i] = (zb + i) % 3;
+      d[0] = rf;
+      g[0] = rg;
+      // an opaque zero added to the LDS base each plane keeps the compiler
+      // from hoisting plane-invariant tap addresses out of the z loop (19
+      // fewer VGPRs, 228 in all)
+      int zero = 0;
+      asm volatile("" : "+v"(zero));
+      ipull_all<M>(lds + zero, q, a, d, g, slots);
+    }
+    // the rest populations of the next plane come straight to registers
+    R nf = R(0), ng = R(0);
+    if (more) {
+      nf = *reinterpret_cast<const float*>(atb(opaque_base(fi + (z + 1) * zsf), cxyf));
+      ng = *reinterpret_cast<const float*>(atb(opaque_base(gi + (z + 1) * zsg), cxyg));
+    }
+    __syncthreads();  // every pull of plane z has read the slots refilled next
+    if (more) dma_class<M, false>(lds, fin, gin, offf, offg, a, z + 1, 0, slots);
+    if (newz) dma_class<M, true>(lds, fin, gin, offf, offg, a, zbn + 2, (zbn + 2) % 3, slots);
+    if (in) {
+      Macro<R> m;
+      collide<3>(d, g, a.k, m);
+      char* const fz = opaque_base(fo + z * zsf);
+      char* const gz = opaque_base(go + z * zsg);
+#pragma unroll
+      for (int i = 0; i < LF::Q; ++i)
+        store_pop<S, NTS>(reinterpret_cast<float*>(atb(fz + i * ps4, cxyf)), d[i], 0u, i);
+#pragma unroll
+      for (int i = 0; i < LG::Q; ++i)
+        store_pop<S, NTS>(reinterpret_cast<float*>(atb(gz + i * ps4, cxyg)), g[i], 0u, 32 + i);
+      if constexpr (REDUCE) red_node(acc, a, q.g, m);
+    }
+    rf = nf;
+    rg = ng;
+    dma_wait();
+    __syncthreads();
+  }
+  if constexpr (REDUCE) red_block<M::NT>(acc, a.inv_uf, a.partials + (long long)blockIdx.x * kRedSlots);
+}
+
 // Tile shapes per lattice, arithmetic width and working-set class (TX x TY x
 // TZ nodes, NR nodes per thread).  "Large" means the two population buffers
 // do not fit the 256 MB last-level cache: those launches use larger 2-D
@@ -1278,6 +1569,39 @@ static hipError_t dispatch_march(const DevState& s, const void* fin, const void*
                 : launch_march_t<S, LARGE, false>(s, fin, gin, fout, gout, partials, st);
 }
 
+// Stretched 3-D meshes with collision and FP32 storage use the interpolating
+// marching kernel.
+// Same column and segment as the uniform marching kernel (measured on
+// 256^3 / 384^3 tanh: 32 x 8 x 32 20.6k / 22.1k MLUPS; 32 x 8 x 64
+// 19.9k / 21.5k; 32 x 4 x 32 20.3k / 21.9k; 32 x 4 x 64 18.3k / 21.4k).
+using IMarch3 = March3;
+
+static int imarch_grid(const DevState& s, int* tiles) { return march_grid(s, tiles); }
+
+static bool use_imarch(const DevState& s) {
+  return s.dim == 3 && s.storage == 0 && s.uniform == 0 && s.collide != 0;
+}
+
+template <bool LARGE, bool RED>
+static hipError_t launch_imarch_t(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
+                                  double* partials, hipStream_t st) {
+  KArgs<float> a = make_args<float>(s);
+  const int nb = imarch_grid(s, a.tiles);
+  a.nblocks = nb;
+  a.partials = partials;
+  hipLaunchKernelGGL((imarch3d_kernel<IMarch3, RED, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
+                     static_cast<const float*>(fin), static_cast<const float*>(gin), static_cast<float*>(fout),
+                     static_cast<float*>(gout), a);
+  return hipGetLastError();
+}
+
+template <bool LARGE>
+static hipError_t dispatch_imarch(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
+                                  bool reduce, double* partials, hipStream_t st) {
+  return reduce ? launch_imarch_t<LARGE, true>(s, fin, gin, fout, gout, partials, st)
+                : launch_imarch_t<LARGE, false>(s, fin, gin, fout, gout, partials, st);
+}
+
 template <typename Fn>
 static hipError_t by_storage(int storage, int dim, Fn&& fn) {
   (void)dim;
@@ -1312,6 +1636,10 @@ int step_blocks(const DevState& s) {
     int tiles[3];
     return march_grid(s, tiles);
   }
+  if (use_imarch(s)) {
+    int tiles[3];
+    return imarch_grid(s, tiles);
+  }
   return lg ? blocks_for<3, float, true>(s) : blocks_for<3, float, false>(s);
 }
 
@@ -1332,6 +1660,10 @@ hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void
       if (use_march(s))
         return s.large ? dispatch_march<S, true>(s, fin, gin, fout, gout, reduce, partials, st)
                        : dispatch_march<S, false>(s, fin, gin, fout, gout, reduce, partials, st);
+      if constexpr (std::is_same_v<S, float>)
+        if (use_imarch(s))
+          return s.large ? dispatch_imarch<true>(s, fin, gin, fout, gout, reduce, partials, st)
+                         : dispatch_imarch<false>(s, fin, gin, fout, gout, reduce, partials, st);
       if (s.dim == 3)
         return s.large ? dispatch_step<3, S, true>(s, fin, gin, fout, gout, reduce, partials, st)
                        : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
