@@ -1159,7 +1159,7 @@ __global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fi
 // the wave's LDS base + 4 l), which need no staging registers: after the
 // pulls of plane z (and a barrier) the next plane's loads are issued into the
 // freed slots and land while plane z collides and is stored.  Measured on
-// 256^3 / 384^3 tanh meshes: 20.6k / 22.1k MLUPS against 20.6k / 20.2k for
+// 256^3 / 384^3 tanh meshes: 22.9k / 22.6k MLUPS against 20.6k / 20.2k for
 // step_kernel's 32 x 4 x 4 tiles.
 // ---------------------------------------------------------------------------
 // A workgroup-uniform plane base made opaque to the optimiser (kept in
@@ -1305,7 +1305,7 @@ __device__ __forceinline__ void dma_class(float* lds, const float* fin, const fl
 // follows makes every wave's loads visible
 __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-template <class M, bool REDUCE, bool NTS>
+template <class M, bool NTS>
 __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict__ fin, const float* __restrict__ gin,
                                                          float* __restrict__ fout, float* __restrict__ gout,
                                                          KArgs<float> a) {
@@ -1376,9 +1376,6 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
   dma_wait();
   __syncthreads();
 
-  RedAcc<R> acc;
-  if constexpr (REDUCE) red_init(acc);
-
 #pragma unroll 1
   for (int z = z0; z < z1; ++z) {
     const bool more = z + 1 < z1;
@@ -1405,8 +1402,8 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
       d[0] = rf;
       g[0] = rg;
       // an opaque zero added to the LDS base each plane keeps the compiler
-      // from hoisting plane-invariant tap addresses out of the z loop (19
-      // fewer VGPRs, 228 in all)
+      // from hoisting plane-invariant tap addresses out of the z loop (about
+      // 20 fewer VGPRs)
       int zero = 0;
       asm volatile("" : "+v"(zero));
       ipull_all<M>(lds + zero, q, a, d, g, slots);
@@ -1431,14 +1428,12 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
 #pragma unroll
       for (int i = 0; i < LG::Q; ++i)
         store_pop<S, NTS>(reinterpret_cast<float*>(atb(gz + i * ps4, cxyg)), g[i], 0u, 32 + i);
-      if constexpr (REDUCE) red_node(acc, a, q.g, m);
     }
     rf = nf;
     rg = ng;
     dma_wait();
     __syncthreads();
   }
-  if constexpr (REDUCE) red_block<M::NT>(acc, a.inv_uf, a.partials + (long long)blockIdx.x * kRedSlots);
 }
 
 // Tile shapes per lattice, arithmetic width and working-set class (TX x TY x
@@ -1571,35 +1566,38 @@ static hipError_t dispatch_march(const DevState& s, const void* fin, const void*
 
 // Stretched 3-D meshes with collision and FP32 storage use the interpolating
 // marching kernel.
-// Same column and segment as the uniform marching kernel (measured on
-// 256^3 / 384^3 tanh: 32 x 8 x 32 20.6k / 22.1k MLUPS; 32 x 8 x 64
-// 19.9k / 21.5k; 32 x 4 x 32 20.3k / 21.9k; 32 x 4 x 64 18.3k / 21.4k).
-using IMarch3 = March3;
+// 64 x 8 columns, 32 planes per segment, one 512-thread workgroup per CU
+// (110 KB of LDS).  Measured on 256^3 / 384^3 tanh meshes (MLUPS; FETCH_SIZE
+// over the algorithmic reads on 256^3): 64 x 8 x 32 22.9k / 22.6k, 1.04x;
+// 32 x 8 x 32 20.6k / 22.1k, 1.32x; 32 x 16 x 32 20.6k / 21.3k, 1.14x;
+// 32 x 8 x 64 19.9k / 21.5k; 32 x 4 x 32 20.3k / 21.9k.  Wider rows leave
+// fewer x-halo cache lines and y-halo rows to fetch beyond L2.
+using IMarch3 = March<64, 8, 32>;
 
-static int imarch_grid(const DevState& s, int* tiles) { return march_grid(s, tiles); }
+static int imarch_grid(const DevState& s, int* tiles) {
+  tiles[0] = (s.n[0] + IMarch3::TX - 1) / IMarch3::TX;
+  tiles[1] = (s.n[1] + IMarch3::TY - 1) / IMarch3::TY;
+  tiles[2] = (s.n[2] + IMarch3::ZS - 1) / IMarch3::ZS;
+  return tiles[0] * tiles[1] * tiles[2];
+}
 
 static bool use_imarch(const DevState& s) {
   return s.dim == 3 && s.storage == 0 && s.uniform == 0 && s.collide != 0;
 }
 
-template <bool LARGE, bool RED>
-static hipError_t launch_imarch_t(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
-                                  double* partials, hipStream_t st) {
+// Plain launches only: the statistics of the reducing launch would hold 13
+// FP64 accumulators across the march and push it beyond 256 VGPRs, so that
+// launch stays with step_kernel (once per call).
+template <bool LARGE>
+static hipError_t launch_imarch(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
+                                hipStream_t st) {
   KArgs<float> a = make_args<float>(s);
   const int nb = imarch_grid(s, a.tiles);
   a.nblocks = nb;
-  a.partials = partials;
-  hipLaunchKernelGGL((imarch3d_kernel<IMarch3, RED, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
+  hipLaunchKernelGGL((imarch3d_kernel<IMarch3, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
                      static_cast<const float*>(fin), static_cast<const float*>(gin), static_cast<float*>(fout),
                      static_cast<float*>(gout), a);
   return hipGetLastError();
-}
-
-template <bool LARGE>
-static hipError_t dispatch_imarch(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
-                                  bool reduce, double* partials, hipStream_t st) {
-  return reduce ? launch_imarch_t<LARGE, true>(s, fin, gin, fout, gout, partials, st)
-                : launch_imarch_t<LARGE, false>(s, fin, gin, fout, gout, partials, st);
 }
 
 template <typename Fn>
@@ -1636,10 +1634,6 @@ int step_blocks(const DevState& s) {
     int tiles[3];
     return march_grid(s, tiles);
   }
-  if (use_imarch(s)) {
-    int tiles[3];
-    return imarch_grid(s, tiles);
-  }
   return lg ? blocks_for<3, float, true>(s) : blocks_for<3, float, false>(s);
 }
 
@@ -1661,9 +1655,9 @@ hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void
         return s.large ? dispatch_march<S, true>(s, fin, gin, fout, gout, reduce, partials, st)
                        : dispatch_march<S, false>(s, fin, gin, fout, gout, reduce, partials, st);
       if constexpr (std::is_same_v<S, float>)
-        if (use_imarch(s))
-          return s.large ? dispatch_imarch<true>(s, fin, gin, fout, gout, reduce, partials, st)
-                         : dispatch_imarch<false>(s, fin, gin, fout, gout, reduce, partials, st);
+        if (use_imarch(s) && !reduce)
+          return s.large ? launch_imarch<true>(s, fin, gin, fout, gout, st)
+                         : launch_imarch<false>(s, fin, gin, fout, gout, st);
       if (s.dim == 3)
         return s.large ? dispatch_step<3, S, true>(s, fin, gin, fout, gout, reduce, partials, st)
                        : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
