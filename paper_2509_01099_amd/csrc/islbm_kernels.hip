@@ -855,17 +855,11 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
 }
 
 // ---------------------------------------------------------------------------
-// 3-D marching variant for uniform meshes (where the interpolation reduces to
-// a shift by one node).  A workgroup owns a TX x TY column of the mesh and
-// walks along z through a segment of ZS planes, one node per thread per
-// plane.  Populations without a z component keep one plane (plus their x/y
-// halo) in LDS; populations with a z component keep a ring of three planes.
-// While a plane is computed, the loads of the next plane are already in
-// flight in registers, so global latency overlaps the collision and z halos
-// are never re-read.  With interpolation weights and 3-tap stencils the
-// same scheme needs about 360 registers per thread, which halves occupancy
-// and is slower than the tile kernel; stretched meshes therefore use
-// step_kernel.
+// Geometry of the 3-D z-march (imarch3d_kernel below).  A workgroup owns a
+// TX x TY column of the mesh and walks along z through a segment of ZS
+// planes, one node per thread per plane.  Populations without a z component
+// keep one plane (plus their x/y halo) in LDS; populations with a z
+// component keep a ring of three planes.
 // ---------------------------------------------------------------------------
 template <int TX_, int TY_, int ZS_>
 struct March {
@@ -929,230 +923,10 @@ __device__ __forceinline__ void mplan(unsigned* offf, unsigned* offg, const KArg
   }
 }
 
-template <class M, int s, typename S, typename R>
-__device__ __forceinline__ void issue_plane(R* regs, const S* __restrict__ fin, const S* __restrict__ gin,
-                                            const unsigned* offf, const unsigned* offg, const KArgs<R>& a,
-                                            int gz) {
-  using SL = Slots<3, typename M::T>;
-  using MS = MStage<M>;
-  using MSH = MShapes<M>;
-  constexpr int m = MSH::of(s);
-  static_assert(MS::iters(s) == MSH::iters(m), "plane boxes of a slot and its shape agree");
-  const bool g = SL::isg(s);
-  const long long rs = g ? a.rsg : a.rsf;
-  const char* base = reinterpret_cast<const char*>((g ? gin : fin) + (long long)SL::pop(s) * a.ps +
-                                                   (long long)gz * a.n[1] * rs);
-  const unsigned* off = (g ? offg : offf) + MSH::ooff(m);
-#pragma unroll
-  for (int k = 0; k < MS::iters(s); ++k)
-    regs[MS::roff(s) + k] = Store<S>::ld(reinterpret_cast<const S*>(atb(base, off[k])));
-}
-
-template <class M, int s, typename R>
-__device__ __forceinline__ void commit_plane(R* lds, const R* regs, int ring) {
-  using SL = Slots<3, typename M::T>;
-  using MS = MStage<M>;
-  constexpr int V = MS::plane(s);
-  R* dst = lds + SL::off(s) + (SL::e(s, 2) != 0 ? ring * V : 0);
-#pragma unroll
-  for (int k = 0; k < MS::iters(s); ++k) {
-    const int idx = threadIdx.x + k * M::NT;
-    if (V % M::NT == 0 || k + 1 < MS::iters(s) || idx < V) dst[idx] = regs[MS::roff(s) + k];
-  }
-}
-
-// Issue / commit the slots of one class (ZC = true: slots with a z component).
-template <class M, bool ZC, typename S, typename R, int... SS>
-__device__ __forceinline__ void issue_class(R* regs, const S* fin, const S* gin, const unsigned* offf,
-                                            const unsigned* offg, const KArgs<R>& a, int gz,
-                                            std::integer_sequence<int, SS...>) {
-  using SL = Slots<3, typename M::T>;
-  ([&] {
-    if constexpr ((SL::e(SS, 2) != 0) == ZC) issue_plane<M, SS, S, R>(regs, fin, gin, offf, offg, a, gz);
-  }(), ...);
-}
-
-template <class M, bool ZC, typename R, int... SS>
-__device__ __forceinline__ void commit_class(R* lds, const R* regs, int ring, std::integer_sequence<int, SS...>) {
-  using SL = Slots<3, typename M::T>;
-  ([&] {
-    if constexpr ((SL::e(SS, 2) != 0) == ZC) commit_plane<M, SS, R>(lds, regs, ring);
-  }(), ...);
-}
-
-struct MGeo {
-  int g[3];
-  int own[2];      // own node in an unshifted x/y frame
-  int ownh[2];     // own node in a shifted x/y frame
-  int dep[2][2];   // departure node (+1, -1) in the shifted x/y frame
-  int ringown;     // ring slot of the own plane z
-  int ringdep[2];  // ring slot of plane z - 1 (+1) and z + 1 (-1)
-};
-
-template <class M, int s, typename R>
-__device__ __forceinline__ R mpull_slot(const R* lds, const MGeo& q) {
-  using SL = Slots<3, typename M::T>;
-  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
-  constexpr int W = SL::ext(s, 0), P = MStage<M>::plane(s);
-  const R* L = lds + SL::off(s);
-  const int ix = ex ? q.dep[0][ex > 0 ? 0 : 1] : q.own[0];
-  const int iy = ey ? q.dep[1][ey > 0 ? 0 : 1] : q.own[1];
-  const int iz = ez ? q.ringdep[ez > 0 ? 0 : 1] : 0;
-  return L[ix + iy * W + iz * P];
-}
-
-template <class M, int s, typename R>
-__device__ __forceinline__ void mwall_slot(const R* lds, const MGeo& q, const KArgs<R>& a, R& val) {
-  using SL = Slots<3, typename M::T>;
-  constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
-  const bool wall = (ex == 1 && q.g[0] == 0) || (ex == -1 && q.g[0] == a.n[0] - 1) ||
-                    (ey == 1 && q.g[1] == 0) || (ey == -1 && q.g[1] == a.n[1] - 1) ||
-                    (ez == 1 && q.g[2] == 0) || (ez == -1 && q.g[2] == a.n[2] - 1);
-  if (!wall) return;
-  constexpr int so = SL::opps(s);
-  constexpr int W = SL::ext(so, 0), P = MStage<M>::plane(so);
-  const int ix = ex ? q.ownh[0] : q.own[0];
-  const int iy = ey ? q.ownh[1] : q.own[1];
-  const int iz = ez ? q.ringown : 0;
-  const R back = lds[SL::off(so) + ix + iy * W + iz * P];
-  if constexpr (SL::isg(s) && ex != 0) {
-    const R Tw = (ex == 1) ? a.Thot : a.Tcold;
-    val = -back + a.omega * Tw;
-  } else {
-    val = back;
-  }
-}
-
-template <class M, typename R, int... SS>
-__device__ __forceinline__ void mpull_all(const R* lds, const MGeo& q, const KArgs<R>& a, R* d, R* g,
-                                          std::integer_sequence<int, SS...>) {
-  using SL = Slots<3, typename M::T>;
-  ((SL::isg(SS) ? (g[SL::pop(SS)] = mpull_slot<M, SS>(lds, q)) : (d[SL::pop(SS)] = mpull_slot<M, SS>(lds, q))),
-   ...);
-  const bool edge = q.g[0] == 0 || q.g[0] == a.n[0] - 1 || q.g[1] == 0 || q.g[1] == a.n[1] - 1 ||
-                    q.g[2] == 0 || q.g[2] == a.n[2] - 1;
-  if (edge) (mwall_slot<M, SS>(lds, q, a, SL::isg(SS) ? g[SL::pop(SS)] : d[SL::pop(SS)]), ...);
-}
-
-template <class M, typename S, bool REDUCE, bool NTS>
-__global__ void __launch_bounds__(M::NT) march3d_kernel(const S* __restrict__ fin, const S* __restrict__ gin,
-                                                        S* __restrict__ fout, S* __restrict__ gout,
-                                                        KArgs<typename Store<S>::R> a) {
-  using R = typename Store<S>::R;
-  using SL = Slots<3, typename M::T>;
-  using LF = typename SL::LF;
-  using LG = typename SL::LG;
-  using MS = MStage<M>;
-  __shared__ R lds[SL::total];
-  constexpr auto slots = std::make_integer_sequence<int, SL::N>{};
-  const unsigned dkey = dither_key<S>(a);
-
-  // column and z segment of this workgroup (XCD-aware numbering as in step_kernel)
-  const int b = blockIdx.x;
-  const int xcd = b & 7, loc = b >> 3;
-  const int per = a.nblocks >> 3, rem = a.nblocks & 7;
-  const int lb = xcd * per + (xcd < rem ? xcd : rem) + loc;
-  const int cols = a.tiles[0] * a.tiles[1];
-  const int col = lb % cols, seg = lb / cols;
-  TileOrigin o;
-  o.t0[0] = (col % a.tiles[0]) * M::TX;
-  o.t0[1] = (col / a.tiles[0]) * M::TY;
-  o.t0[2] = 0;
-  o.lo[0] = clampi(o.t0[0] - 1, 0, a.n[0] - 3);
-  o.lo[1] = clampi(o.t0[1] - 1, 0, a.n[1] - 3);
-  o.lo[2] = 0;
-  const int nz = a.n[2];
-  const int z0 = seg * M::ZS;
-  const int z1 = min(nz, z0 + M::ZS);
-
-  MGeo q;
-  const int lx = threadIdx.x % M::TX, ly = threadIdx.x / M::TX;
-  q.g[0] = o.t0[0] + lx;
-  q.g[1] = o.t0[1] + ly;
-  q.own[0] = lx;
-  q.own[1] = ly;
-  q.ownh[0] = q.g[0] - o.lo[0];
-  q.ownh[1] = q.g[1] - o.lo[1];
-  const bool in = q.g[0] < a.n[0] && q.g[1] < a.n[1];
-  if (in) {
-#pragma unroll
-    for (int ax = 0; ax < 2; ++ax) {
-      q.dep[ax][0] = q.g[ax] == 0 ? q.ownh[ax] : q.ownh[ax] - 1;
-      q.dep[ax][1] = q.g[ax] == a.n[ax] - 1 ? q.ownh[ax] : q.ownh[ax] + 1;
-    }
-  }
-  const long long gy0 = in ? q.g[1] : 0, gx0 = in ? q.g[0] : 0;
-  const long long cxyf = gy0 * a.rsf + gx0, cxyg = gy0 * a.rsg + gx0;
-  const long long zsf = (long long)a.n[1] * a.rsf, zsg = (long long)a.n[1] * a.rsg;
-
-  // in-plane staging offsets (once), then the prologue: the three stencil
-  // planes of z0 and the x/y planes of z0
-  unsigned offf[MShapes<M>::total], offg[MShapes<M>::total];
-  mplan<M, S, R>(offf, offg, a, o);
-  R regs[MS::total];
-  const int zb0 = clampi(z0 - 1, 0, nz - 3);
-#pragma unroll 1
-  for (int p = 0; p < 3; ++p) {
-    issue_class<M, true, S, R>(regs, fin, gin, offf, offg, a, zb0 + p, slots);
-    commit_class<M, true, R>(lds, regs, (zb0 + p) % 3, slots);
-  }
-  issue_class<M, false, S, R>(regs, fin, gin, offf, offg, a, z0, slots);
-  R rf = Store<S>::ld(fin + (long long)z0 * zsf + cxyf);
-  R rg = Store<S>::ld(gin + (long long)z0 * zsg + cxyg);
-  commit_class<M, false, R>(lds, regs, 0, slots);
-  __syncthreads();
-
-  RedAcc<R> acc;
-  if constexpr (REDUCE) red_init(acc);
-
-#pragma unroll 1
-  for (int z = z0; z < z1; ++z) {
-    const bool more = z + 1 < z1;
-    const int zb = clampi(z - 1, 0, nz - 3);
-    const int zbn = clampi(z, 0, nz - 3);
-    const bool newz = more && zbn > zb;
-    // prefetch the next plane
-    R nf = R(0), ng = R(0);
-    if (more) {
-      issue_class<M, false, S, R>(regs, fin, gin, offf, offg, a, z + 1, slots);
-      nf = Store<S>::ld(fin + (long long)(z + 1) * zsf + cxyf);
-      ng = Store<S>::ld(gin + (long long)(z + 1) * zsg + cxyg);
-    }
-    if (newz) issue_class<M, true, S, R>(regs, fin, gin, offf, offg, a, zbn + 2, slots);
-
-    if (in) {
-      q.g[2] = z;
-      q.ringown = z % 3;
-      q.ringdep[0] = z == 0 ? q.ringown : (z - 1) % 3;
-      q.ringdep[1] = z == nz - 1 ? q.ringown : (z + 1) % 3;
-      R d[LF::Q], g[LG::Q];
-      d[0] = rf;
-      g[0] = rg;
-      mpull_all<M>(lds, q, a, d, g, slots);
-      Macro<R> m;
-      collide<3>(d, g, a.k, m);
-      const long long hc = ((long long)z * a.n[1] + gy0) * a.pitch + gx0;
-      const unsigned h0 = Store<S>::kDither ? mix32(unsigned(hc) ^ dkey) : 0u;
-      const long long cf = (long long)z * zsf + cxyf, cg = (long long)z * zsg + cxyg;
-#pragma unroll
-      for (int i = 0; i < LF::Q; ++i) store_pop<S, NTS>(fout + (long long)i * a.ps + cf, d[i], h0, i);
-#pragma unroll
-      for (int i = 0; i < LG::Q; ++i) store_pop<S, NTS>(gout + (long long)i * a.ps + cg, g[i], h0, 32 + i);
-      if constexpr (REDUCE) red_node(acc, a, q.g, m);
-    }
-    __syncthreads();
-    if (more) commit_class<M, false, R>(lds, regs, 0, slots);
-    if (newz) commit_class<M, true, R>(lds, regs, (zbn + 2) % 3, slots);
-    rf = nf;
-    rg = ng;
-    __syncthreads();
-  }
-  if constexpr (REDUCE) red_block<M::NT>(acc, a.inv_uf, a.partials + (long long)blockIdx.x * kRedSlots);
-}
-
 // ---------------------------------------------------------------------------
-// 3-D marching variant for stretched meshes (FP32 storage): the column and
-// plane ring of march3d_kernel, with the interpolated pulls of step_kernel.
+// 3-D marching kernel (FP32 storage, plain launches): the column and plane
+// ring above, with the interpolated pulls of step_kernel (or, on a uniform
+// mesh, the shift by one node).
 // The ring already holds the three stencil planes zb .. zb + 2 of plane z
 // (zb = clamp(z - 1, 0, nz - 3)), so z halos are read once per column.  The
 // planes are staged with direct global -> LDS loads (lane l of a wave writes
@@ -1187,13 +961,23 @@ struct IGeo {
   float wm[3][3];   // weights, direction -1
   int ring[3];      // ring slots of the stencil planes zb, zb + 1, zb + 2
   int ringown;      // ring slot of plane z
+  int dep[2][2];    // uniform mesh: departure node x - e (+1, -1) in the shifted x/y frame,
+                    // clamped into the frame for links that leave the fluid
+  int ringdep[2];   // uniform mesh: ring slot of plane z - 1 (+1) and z + 1 (-1), clamped
 };
 
-template <class M, int s>
+template <class M, int s, bool UNI>
 __device__ __forceinline__ float ipull_slot(const float* lds, const IGeo& q) {
   using SL = Slots<3, typename M::T>;
   constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
   constexpr int W = SL::ext(s, 0), P = MStage<M>::plane(s);
+  if constexpr (UNI) {
+    // departure node x - e (the clamped indices keep wall links in range)
+    const int ix = ex ? q.dep[0][ex > 0 ? 0 : 1] : q.own[0];
+    const int iy = ey ? q.dep[1][ey > 0 ? 0 : 1] : q.own[1];
+    const int iz = ez ? q.ringdep[ez > 0 ? 0 : 1] : 0;
+    return lds[SL::off(s) + ix + iy * W + iz * P];
+  }
   const int ix = ex ? q.base[0] : q.own[0];
   const int iy = ey ? q.base[1] : q.own[1];
   const float* Pxy = lds + SL::off(s) + ix + iy * W;
@@ -1254,11 +1038,12 @@ __device__ __forceinline__ void iwall_slot(const float* lds, const IGeo& q, cons
   }
 }
 
-template <class M, int... SS>
+template <class M, bool UNI, int... SS>
 __device__ __forceinline__ void ipull_all(const float* lds, const IGeo& q, const KArgs<float>& a, float* d,
                                           float* g, std::integer_sequence<int, SS...>) {
   using SL = Slots<3, typename M::T>;
-  ((SL::isg(SS) ? (g[SL::pop(SS)] = ipull_slot<M, SS>(lds, q)) : (d[SL::pop(SS)] = ipull_slot<M, SS>(lds, q))),
+  ((SL::isg(SS) ? (g[SL::pop(SS)] = ipull_slot<M, SS, UNI>(lds, q))
+                : (d[SL::pop(SS)] = ipull_slot<M, SS, UNI>(lds, q))),
    ...);
   const bool edge = q.g[0] == 0 || q.g[0] == a.n[0] - 1 || q.g[1] == 0 || q.g[1] == a.n[1] - 1 ||
                     q.g[2] == 0 || q.g[2] == a.n[2] - 1;
@@ -1305,7 +1090,7 @@ __device__ __forceinline__ void dma_class(float* lds, const float* fin, const fl
 // follows makes every wave's loads visible
 __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-template <class M, bool NTS>
+template <class M, bool UNI, bool NTS>
 __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict__ fin, const float* __restrict__ gin,
                                                          float* __restrict__ fout, float* __restrict__ gout,
                                                          KArgs<float> a) {
@@ -1347,8 +1132,13 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
   if (in) {
 #pragma unroll
     for (int ax = 0; ax < 2; ++ax) {
-      q.base[ax] = clampi(q.g[ax] - 1, 0, a.n[ax] - 3) - o.lo[ax];
-      load_weights(a.wtab[ax], a.n[ax], q.g[ax], q.wp[ax], q.wm[ax]);
+      if constexpr (UNI) {
+        q.dep[ax][0] = q.g[ax] == 0 ? q.ownh[ax] : q.ownh[ax] - 1;
+        q.dep[ax][1] = q.g[ax] == a.n[ax] - 1 ? q.ownh[ax] : q.ownh[ax] + 1;
+      } else {
+        q.base[ax] = clampi(q.g[ax] - 1, 0, a.n[ax] - 3) - o.lo[ax];
+        load_weights(a.wtab[ax], a.n[ax], q.g[ax], q.wp[ax], q.wm[ax]);
+      }
     }
   }
   // every global access is a workgroup-uniform base (plane z of one
@@ -1386,7 +1176,7 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
     // z weights of the plane: uniform, read through the scalar cache (a
     // vector load here would make its wait also wait for the previous
     // plane's stores, which complete in order with it)
-    {
+    if constexpr (!UNI) {
       const CFloat* wz = (const CFloat*)(opaque_base(a.wtab[2]));  // 4 floats per node and direction
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -1399,6 +1189,8 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
       q.ringown = z % 3;
 #pragma unroll
       for (int i = 0; i < 3; ++i) q.ring[i] = (zb + i) % 3;
+      q.ringdep[0] = z == 0 ? q.ringown : (z - 1) % 3;
+      q.ringdep[1] = z == nz - 1 ? q.ringown : (z + 1) % 3;
       d[0] = rf;
       g[0] = rg;
       // an opaque zero added to the LDS base each plane keeps the compiler
@@ -1406,7 +1198,7 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
       // 20 fewer VGPRs)
       int zero = 0;
       asm volatile("" : "+v"(zero));
-      ipull_all<M>(lds + zero, q, a, d, g, slots);
+      ipull_all<M, UNI>(lds + zero, q, a, d, g, slots);
     }
     // the rest populations of the next plane come straight to registers
     R nf = R(0), ng = R(0);
@@ -1526,47 +1318,10 @@ static hipError_t dispatch_step(const DevState& s, const void* fin, const void* 
                 : launch_step_t<D, S, LARGE, false, false, false>(s, fin, gin, fout, gout, partials, st);
 }
 
-// Uniform 3-D meshes with collision and FP32 storage use the z-marching
-// kernel.  FP16 / BF16 storage keeps the tile kernel, whose 2-byte tiles
-// (paired staging, half-precision LDS for FP16) outrun the marching kernel's
-// FP32 plane ring for these types.
-using March3 = March<32, 8, 32>;
-
-static bool use_march(const DevState& s) {
-  return s.dim == 3 && s.storage == 0 && s.uniform != 0 && s.collide != 0;
-}
-
-static int march_grid(const DevState& s, int* tiles) {
-  tiles[0] = (s.n[0] + March3::TX - 1) / March3::TX;
-  tiles[1] = (s.n[1] + March3::TY - 1) / March3::TY;
-  tiles[2] = (s.n[2] + March3::ZS - 1) / March3::ZS;
-  return tiles[0] * tiles[1] * tiles[2];
-}
-
-template <typename S, bool LARGE, bool RED>
-static hipError_t launch_march_t(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
-                                 double* partials, hipStream_t st) {
-  using R = typename Store<S>::R;
-  KArgs<R> a = make_args<R>(s);
-  const int nb = march_grid(s, a.tiles);
-  a.nblocks = nb;
-  a.partials = partials;
-  hipLaunchKernelGGL((march3d_kernel<March3, S, RED, LARGE>), dim3(nb), dim3(March3::NT), 0, st,
-                     static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
-                     static_cast<S*>(gout), a);
-  return hipGetLastError();
-}
-
-template <typename S, bool LARGE>
-static hipError_t dispatch_march(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
-                                 bool reduce, double* partials, hipStream_t st) {
-  return reduce ? launch_march_t<S, LARGE, true>(s, fin, gin, fout, gout, partials, st)
-                : launch_march_t<S, LARGE, false>(s, fin, gin, fout, gout, partials, st);
-}
-
-// Stretched 3-D meshes with collision and FP32 storage use the interpolating
-// marching kernel.
-// 64 x 8 columns, 32 planes per segment, one 512-thread workgroup per CU
+// 3-D meshes with collision and FP32 storage use the marching kernel for
+// their plain launches (FP16 / BF16 storage keeps the tile kernel, whose
+// 2-byte tiles with paired staging and, for FP16, half-precision LDS suit
+// those types better).  64 x 8 columns, 32 planes per segment, one 512-thread workgroup per CU
 // (110 KB of LDS).  Measured on 256^3 / 384^3 tanh meshes (MLUPS; FETCH_SIZE
 // over the algorithmic reads on 256^3): 64 x 8 x 32 22.9k / 22.6k, 1.04x;
 // 32 x 8 x 32 20.6k / 22.1k, 1.32x; 32 x 16 x 32 20.6k / 21.3k, 1.14x;
@@ -1582,7 +1337,7 @@ static int imarch_grid(const DevState& s, int* tiles) {
 }
 
 static bool use_imarch(const DevState& s) {
-  return s.dim == 3 && s.storage == 0 && s.uniform == 0 && s.collide != 0;
+  return s.dim == 3 && s.storage == 0 && s.collide != 0;
 }
 
 // Plain launches only: the statistics of the reducing launch would hold 13
@@ -1594,9 +1349,14 @@ static hipError_t launch_imarch(const DevState& s, const void* fin, const void* 
   KArgs<float> a = make_args<float>(s);
   const int nb = imarch_grid(s, a.tiles);
   a.nblocks = nb;
-  hipLaunchKernelGGL((imarch3d_kernel<IMarch3, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
-                     static_cast<const float*>(fin), static_cast<const float*>(gin), static_cast<float*>(fout),
-                     static_cast<float*>(gout), a);
+  if (s.uniform)
+    hipLaunchKernelGGL((imarch3d_kernel<IMarch3, true, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
+                       static_cast<const float*>(fin), static_cast<const float*>(gin), static_cast<float*>(fout),
+                       static_cast<float*>(gout), a);
+  else
+    hipLaunchKernelGGL((imarch3d_kernel<IMarch3, false, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
+                       static_cast<const float*>(fin), static_cast<const float*>(gin), static_cast<float*>(fout),
+                       static_cast<float*>(gout), a);
   return hipGetLastError();
 }
 
@@ -1630,10 +1390,6 @@ int step_blocks(const DevState& s) {
     return lg ? blocks_for<2, float, true>(s) : blocks_for<2, float, false>(s);
   }
   if (dbl) return blocks_for<3, double, false>(s);
-  if (use_march(s)) {
-    int tiles[3];
-    return march_grid(s, tiles);
-  }
   return lg ? blocks_for<3, float, true>(s) : blocks_for<3, float, false>(s);
 }
 
@@ -1651,9 +1407,6 @@ hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void
       return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
                         : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
     } else {
-      if (use_march(s))
-        return s.large ? dispatch_march<S, true>(s, fin, gin, fout, gout, reduce, partials, st)
-                       : dispatch_march<S, false>(s, fin, gin, fout, gout, reduce, partials, st);
       if constexpr (std::is_same_v<S, float>)
         if (use_imarch(s) && !reduce)
           return s.large ? launch_imarch<true>(s, fin, gin, fout, gout, st)
