@@ -47,7 +47,7 @@ TOL = {"fp32": (1e-5, 1e-5), "fp16": (1e-4, 2e-3), "fp32sr": (1e-5, 1e-5), "fp64
     (2, "erf", (4096, 2048), 1e8, "fp64"),         # FP64 beyond 1 GB: streaming stores
     (3, "tanh", (256, 256, 256), 1e7, "fp32sr"),   # the same for FP64 arithmetic in 3-D
     (3, "tanh", (256, 256, 256), 1e7, "fp32"),     # the 3-D workload
-    (3, "uniform", (256, 256, 256), 1e7, "fp32"),  # uniform 3-D: z-marching kernel
+    (3, "uniform", (256, 256, 256), 1e7, "fp32"),  # uniform 3-D: the march with a one-node shift
 ])
 def test_one_step_full_size_sampled(dim, kind, n, Ra, storage):
     oracle.set_threads(16)
