@@ -117,6 +117,9 @@ def test_strerror_and_null_handling():
     assert lib.islbm_strerror(7) == b"unknown status"
     lib.islbm_destroy(None)                  # no-op
     assert lib.islbm_step(None, 1) == pkg.ISLBM_EINVAL
+    assert lib.islbm_plan_steps(None, 20) == pkg.ISLBM_EINVAL
+    assert lib.islbm_time_steps_split(None, 2, None, None, None) == pkg.ISLBM_EINVAL
+    assert lib.islbm_copy_bytes(None, None, 16, None) == pkg.ISLBM_EINVAL
     assert lib.islbm_nu_re(None, None) == pkg.ISLBM_EINVAL
     assert lib.islbm_steady_change(None, None, None, None) == pkg.ISLBM_EINVAL
     assert lib.islbm_time(None) == -1
