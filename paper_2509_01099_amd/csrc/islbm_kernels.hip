@@ -861,23 +861,19 @@ __global__ void __launch_bounds__(T::NT) step_kernel(const S* __restrict__ fin, 
 // keep one plane (plus their x/y halo) in LDS; populations with a z
 // component keep a ring of three planes.
 // ---------------------------------------------------------------------------
-template <int TX_, int TY_, int ZS_>
+template <int TX_, int TY_, int ZS_, int XH_ = 2>
 struct March {
   static constexpr int TX = TX_, TY = TY_, ZS = ZS_, NT = TX * TY;
-  using T = Tile<TX, TY, 1, 1>;  // slot geometry: z-shifted slots hold 3 planes
+  // slot geometry: z-shifted slots hold 3 planes; XH = 4 for 2-byte storage
+  // (x-shifted boxes start at an even x and are staged as 4-byte x pairs)
+  using T = Tile<TX, TY, 1, 1, XH_>;
+  static constexpr int U = XH_ == 4 ? 2 : 1;  // elements per 4-byte load unit
 };
 
 template <class M>
 struct MStage {
   using SL = Slots<3, typename M::T>;
   __host__ __device__ static constexpr int plane(int s) { return SL::ext(s, 0) * SL::ext(s, 1); }
-  __host__ __device__ static constexpr int iters(int s) { return (plane(s) + M::NT - 1) / M::NT; }
-  __host__ __device__ static constexpr int roff(int s) {
-    int o = 0;
-    for (int k = 0; k < s; ++k) o += iters(k);
-    return o;
-  }
-  static constexpr int total = roff(SL::N);
 };
 
 // In-plane staging offsets of the marching kernel: a slot's plane box depends
@@ -885,14 +881,16 @@ struct MStage {
 // shape m = x bit | y bit), so a thread forms its 32-bit byte offsets within
 // a z-plane once per shape and set (they do not change along the march);
 // each plane's loads are then a workgroup-uniform plane base plus these
-// offsets.
+// offsets.  Every load moves one 4-byte unit (one element, or an x pair of
+// 2-byte elements).
 template <class M>
 struct MShapes {
   using SL = Slots<3, typename M::T>;
   __host__ __device__ static constexpr int of(int s) { return (SL::e(s, 0) != 0 ? 1 : 0) | (SL::e(s, 1) != 0 ? 2 : 0); }
-  __host__ __device__ static constexpr int w(int m) { return M::TX + ((m & 1) ? 2 : 0); }
+  __host__ __device__ static constexpr int w(int m) { return M::TX + ((m & 1) ? M::T::XH : 0); }
   __host__ __device__ static constexpr int h(int m) { return M::TY + ((m & 2) ? 2 : 0); }
-  __host__ __device__ static constexpr int iters(int m) { return (w(m) * h(m) + M::NT - 1) / M::NT; }
+  __host__ __device__ static constexpr int units(int m) { return w(m) / M::U * h(m); }
+  __host__ __device__ static constexpr int iters(int m) { return (units(m) + M::NT - 1) / M::NT; }
   __host__ __device__ static constexpr int ooff(int m) {
     int o = 0;
     for (int k = 0; k < m; ++k) o += iters(k);
@@ -904,9 +902,12 @@ struct MShapes {
 template <class M, typename S, typename R>
 __device__ __forceinline__ void mplan(unsigned* offf, unsigned* offg, const KArgs<R>& a, const TileOrigin& o) {
   using MSH = MShapes<M>;
+  constexpr int U = M::U;
+  // last load unit of a row: a pair never starts beyond the last even x
+  const int xmax = U == 2 ? ((a.n[0] - 1) & ~1) : a.n[0] - 1;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const int W = MSH::w(m), V = W * MSH::h(m);
+    const int W = MSH::w(m) / U, V = MSH::units(m);
     const int ox = (m & 1) ? o.lo[0] : o.t0[0];
     const int oy = (m & 2) ? o.lo[1] : o.t0[1];
 #pragma unroll
@@ -915,7 +916,7 @@ __device__ __forceinline__ void mplan(unsigned* offf, unsigned* offg, const KArg
       idx = idx < V ? idx : V - 1;
       const int ly = idx / W;
       const int lx = idx - ly * W;
-      const unsigned gx = unsigned(min(ox + lx, a.n[0] - 1));
+      const unsigned gx = unsigned(min(ox + lx * U, xmax));
       const unsigned gy = unsigned(min(oy + ly, a.n[1] - 1));
       offf[MSH::ooff(m) + k] = (__umul24(gy, unsigned(a.rsf)) + gx) * unsigned(sizeof(S));
       offg[MSH::ooff(m) + k] = (__umul24(gy, unsigned(a.rsg)) + gx) * unsigned(sizeof(S));
@@ -924,9 +925,9 @@ __device__ __forceinline__ void mplan(unsigned* offf, unsigned* offg, const KArg
 }
 
 // ---------------------------------------------------------------------------
-// 3-D marching kernel (FP32 storage, plain launches): the column and plane
-// ring above, with the interpolated pulls of step_kernel (or, on a uniform
-// mesh, the shift by one node).
+// 3-D marching kernel (plain launches; FP32 storage, and FP16 storage on
+// uniform meshes): the column and plane ring above, with the interpolated
+// pulls of step_kernel (or, on a uniform mesh, the shift by one node).
 // The ring already holds the three stencil planes zb .. zb + 2 of plane z
 // (zb = clamp(z - 1, 0, nz - 3)), so z halos are read once per column.  The
 // planes are staged with direct global -> LDS loads (lane l of a wave writes
@@ -966,8 +967,10 @@ struct IGeo {
   int ringdep[2];   // uniform mesh: ring slot of plane z - 1 (+1) and z + 1 (-1), clamped
 };
 
-template <class M, int s, bool UNI>
-__device__ __forceinline__ float ipull_slot(const float* lds, const IGeo& q) {
+// L: the LDS element type (float, or the raw scaled halves of FP16 storage,
+// read through lv / lw as in step_kernel; the caller applies the scale)
+template <class M, int s, bool UNI, typename L>
+__device__ __forceinline__ float ipull_slot(const L* lds, const IGeo& q) {
   using SL = Slots<3, typename M::T>;
   constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
   constexpr int W = SL::ext(s, 0), P = MStage<M>::plane(s);
@@ -976,11 +979,11 @@ __device__ __forceinline__ float ipull_slot(const float* lds, const IGeo& q) {
     const int ix = ex ? q.dep[0][ex > 0 ? 0 : 1] : q.own[0];
     const int iy = ey ? q.dep[1][ey > 0 ? 0 : 1] : q.own[1];
     const int iz = ez ? q.ringdep[ez > 0 ? 0 : 1] : 0;
-    return lds[SL::off(s) + ix + iy * W + iz * P];
+    return lv<float>(lds[SL::off(s) + ix + iy * W + iz * P]);
   }
   const int ix = ex ? q.base[0] : q.own[0];
   const int iy = ey ? q.base[1] : q.own[1];
-  const float* Pxy = lds + SL::off(s) + ix + iy * W;
+  const L* Pxy = lds + SL::off(s) + ix + iy * W;
   const float* wx = ex > 0 ? q.wp[0] : q.wm[0];
   const float* wy = ey > 0 ? q.wp[1] : q.wm[1];
   const float* wz = ez > 0 ? q.wp[2] : q.wm[2];
@@ -988,16 +991,17 @@ __device__ __forceinline__ float ipull_slot(const float* lds, const IGeo& q) {
   if constexpr (nsh == 1 && ez == 0) {
     constexpr int st = ex ? 1 : W;
     const float* w = ex ? wx : wy;
-    return w[0] * Pxy[0] + w[1] * Pxy[st] + w[2] * Pxy[2 * st];
+    return lw(w[0], Pxy[0]) + w[1] * lv<float>(Pxy[st]) + w[2] * lv<float>(Pxy[2 * st]);
   } else if constexpr (nsh == 1) {
-    return wz[0] * Pxy[q.ring[0] * P] + wz[1] * Pxy[q.ring[1] * P] + wz[2] * Pxy[q.ring[2] * P];
+    return lw(wz[0], Pxy[q.ring[0] * P]) + wz[1] * lv<float>(Pxy[q.ring[1] * P]) +
+           wz[2] * lv<float>(Pxy[q.ring[2] * P]);
   } else if constexpr (ez == 0) {
     // x and y: inner axis x, outer y (as in step_kernel)
     float acc = 0.0f;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const float* Pb = Pxy + b * W;
-      const float v = wx[0] * Pb[0] + wx[1] * Pb[1] + wx[2] * Pb[2];
+      const L* Pb = Pxy + b * W;
+      const float v = lw(wx[0], Pb[0]) + wx[1] * lv<float>(Pb[1]) + wx[2] * lv<float>(Pb[2]);
       acc = b == 0 ? wy[0] * v : acc + wy[b] * v;
     }
     return acc;
@@ -1008,16 +1012,17 @@ __device__ __forceinline__ float ipull_slot(const float* lds, const IGeo& q) {
     float acc = 0.0f;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const float* Pb = Pxy + q.ring[b] * P;
-      const float v = w1[0] * Pb[0] + w1[1] * Pb[s1] + w1[2] * Pb[2 * s1];
+      const L* Pb = Pxy + q.ring[b] * P;
+      const float v = lw(w1[0], Pb[0]) + w1[1] * lv<float>(Pb[s1]) + w1[2] * lv<float>(Pb[2 * s1]);
       acc = b == 0 ? wz[0] * v : acc + wz[b] * v;
     }
     return acc;
   }
 }
 
-template <class M, int s>
-__device__ __forceinline__ void iwall_slot(const float* lds, const IGeo& q, const KArgs<float>& a, float& val) {
+template <class M, int s, typename L>
+__device__ __forceinline__ void iwall_slot(const L* lds, const IGeo& q, const KArgs<float>& a, float lscale,
+                                           float& val) {
   using SL = Slots<3, typename M::T>;
   constexpr int ex = SL::e(s, 0), ey = SL::e(s, 1), ez = SL::e(s, 2);
   const bool wall = (ex == 1 && q.g[0] == 0) || (ex == -1 && q.g[0] == a.n[0] - 1) ||
@@ -1029,7 +1034,7 @@ __device__ __forceinline__ void iwall_slot(const float* lds, const IGeo& q, cons
   const int ix = ex ? q.ownh[0] : q.own[0];
   const int iy = ey ? q.ownh[1] : q.own[1];
   const int iz = ez ? q.ringown : 0;
-  const float back = lds[SL::off(so) + ix + iy * W + iz * P];
+  const float back = lv<float>(lds[SL::off(so) + ix + iy * W + iz * P]) * lscale;
   if constexpr (SL::isg(s) && ex != 0) {
     const float Tw = (ex == 1) ? a.Thot : a.Tcold;
     val = -back + a.omega * Tw;
@@ -1038,46 +1043,48 @@ __device__ __forceinline__ void iwall_slot(const float* lds, const IGeo& q, cons
   }
 }
 
-template <class M, bool UNI, int... SS>
-__device__ __forceinline__ void ipull_all(const float* lds, const IGeo& q, const KArgs<float>& a, float* d,
-                                          float* g, std::integer_sequence<int, SS...>) {
+template <class M, bool UNI, typename L, int... SS>
+__device__ __forceinline__ void ipull_all(const L* lds, const IGeo& q, const KArgs<float>& a, float lscale,
+                                          float* d, float* g, std::integer_sequence<int, SS...>) {
   using SL = Slots<3, typename M::T>;
-  ((SL::isg(SS) ? (g[SL::pop(SS)] = ipull_slot<M, SS, UNI>(lds, q))
-                : (d[SL::pop(SS)] = ipull_slot<M, SS, UNI>(lds, q))),
+  ((SL::isg(SS) ? (g[SL::pop(SS)] = ipull_slot<M, SS, UNI>(lds, q) * lscale)
+                : (d[SL::pop(SS)] = ipull_slot<M, SS, UNI>(lds, q) * lscale)),
    ...);
   const bool edge = q.g[0] == 0 || q.g[0] == a.n[0] - 1 || q.g[1] == 0 || q.g[1] == a.n[1] - 1 ||
                     q.g[2] == 0 || q.g[2] == a.n[2] - 1;
-  if (edge) (iwall_slot<M, SS>(lds, q, a, SL::isg(SS) ? g[SL::pop(SS)] : d[SL::pop(SS)]), ...);
+  if (edge) (iwall_slot<M, SS>(lds, q, a, lscale, SL::isg(SS) ? g[SL::pop(SS)] : d[SL::pop(SS)]), ...);
 }
 
 // Direct global -> LDS staging of one slot's plane gz into ring slot `ring`
 // (slots without a z component have one plane).  Lanes past the plane box
 // stay idle; a wave's 64 lanes write 64 consecutive LDS entries.
-template <class M, int s>
-__device__ __forceinline__ void dma_plane(float* lds, const float* __restrict__ fin, const float* __restrict__ gin,
+template <class M, int s, typename S, typename L>
+__device__ __forceinline__ void dma_plane(L* lds, const S* __restrict__ fin, const S* __restrict__ gin,
                                           const unsigned* offf, const unsigned* offg, const KArgs<float>& a,
                                           int gz, int ring) {
   using SL = Slots<3, typename M::T>;
   using MS = MStage<M>;
   using MSH = MShapes<M>;
-  constexpr int m = MSH::of(s), V = MS::plane(s);
+  constexpr int m = MSH::of(s), V = MSH::units(m);
   const bool g = SL::isg(s);
   const long long rs = g ? a.rsg : a.rsf;
   const char* base = opaque_base(reinterpret_cast<const char*>((g ? gin : fin) + (long long)SL::pop(s) * a.ps +
                                                                (long long)gz * a.n[1] * rs));
   const unsigned* off = (g ? offg : offf) + MSH::ooff(m);
-  float* dst = lds + SL::off(s) + (SL::e(s, 2) != 0 ? ring * V : 0) + (threadIdx.x & ~63);
+  // 4-byte load units of this slot's plane (one element, or an x pair)
+  unsigned* dst = reinterpret_cast<unsigned*>(lds + SL::off(s) + (SL::e(s, 2) != 0 ? ring * MS::plane(s) : 0)) +
+                  (threadIdx.x & ~63);
 #pragma unroll
-  for (int k = 0; k < MS::iters(s); ++k) {
+  for (int k = 0; k < MSH::iters(m); ++k) {
     const int idx = threadIdx.x + k * M::NT;
-    if (V % M::NT == 0 || k + 1 < MS::iters(s) || idx < V)
+    if (V % M::NT == 0 || k + 1 < MSH::iters(m) || idx < V)
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(atb(base, off[k])), dst + k * M::NT, 4, 0,
                                        0);
   }
 }
 
-template <class M, bool ZC, int... SS>
-__device__ __forceinline__ void dma_class(float* lds, const float* fin, const float* gin, const unsigned* offf,
+template <class M, bool ZC, typename S, typename L, int... SS>
+__device__ __forceinline__ void dma_class(L* lds, const S* fin, const S* gin, const unsigned* offf,
                                           const unsigned* offg, const KArgs<float>& a, int gz, int ring,
                                           std::integer_sequence<int, SS...>) {
   using SL = Slots<3, typename M::T>;
@@ -1090,16 +1097,21 @@ __device__ __forceinline__ void dma_class(float* lds, const float* fin, const fl
 // follows makes every wave's loads visible
 __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-template <class M, bool UNI, bool NTS>
-__global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict__ fin, const float* __restrict__ gin,
-                                                         float* __restrict__ fout, float* __restrict__ gout,
+template <class M, typename S, bool UNI, bool NTS>
+__global__ void __launch_bounds__(M::NT) imarch3d_kernel(const S* __restrict__ fin, const S* __restrict__ gin,
+                                                         S* __restrict__ fout, S* __restrict__ gout,
                                                          KArgs<float> a) {
-  using S = float;
   using R = float;
+  static_assert(std::is_same_v<typename Store<S>::R, float>, "FP32 arithmetic");
+  using L = typename Lds<3, S>::type;  // float, or the raw scaled halves of FP16 storage
+  static_assert(sizeof(L) == sizeof(S), "the plane loads copy stored values into LDS unchanged");
+  static_assert((M::U == 2) == (sizeof(S) == 2), "2-byte storage is staged in x pairs");
+  const R lscale = Lds<3, S>::kScaled ? R(1.0 / 4096.0) : R(1);
   using SL = Slots<3, typename M::T>;
   using LF = typename SL::LF;
   using LG = typename SL::LG;
-  __shared__ float lds[SL::total];
+  __shared__ __attribute__((aligned(16))) L lds[SL::total];
+  const unsigned dkey = dither_key<S>(a);
   constexpr auto slots = std::make_integer_sequence<int, SL::N>{};
 
   // column and z segment of this workgroup (XCD-aware numbering as in step_kernel)
@@ -1114,6 +1126,7 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
   o.t0[1] = (col / a.tiles[0]) * M::TY;
   o.t0[2] = 0;
   o.lo[0] = clampi(o.t0[0] - 1, 0, a.n[0] - 3);
+  if constexpr (M::U == 2) o.lo[0] &= ~1;  // paired staging: boxes start at an even x
   o.lo[1] = clampi(o.t0[1] - 1, 0, a.n[1] - 3);
   o.lo[2] = 0;
   const int nz = a.n[2];
@@ -1145,9 +1158,10 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
   // population, in scalar registers) plus the thread's 32-bit in-plane byte
   // offset, so no per-population 64-bit address stays live across the march
   const unsigned gy0 = in ? unsigned(q.g[1]) : 0u, gx0 = in ? unsigned(q.g[0]) : 0u;
-  const unsigned cxyf = (__umul24(gy0, unsigned(a.rsf)) + gx0) * 4u, cxyg = (__umul24(gy0, unsigned(a.rsg)) + gx0) * 4u;
-  const long long zsf = (long long)a.n[1] * a.rsf * 4, zsg = (long long)a.n[1] * a.rsg * 4;
-  const long long ps4 = (long long)a.ps * 4;
+  constexpr unsigned SB = sizeof(S);
+  const unsigned cxyf = (__umul24(gy0, unsigned(a.rsf)) + gx0) * SB, cxyg = (__umul24(gy0, unsigned(a.rsg)) + gx0) * SB;
+  const long long zsf = (long long)a.n[1] * a.rsf * SB, zsg = (long long)a.n[1] * a.rsg * SB;
+  const long long ps4 = (long long)a.ps * SB;
   const char* const fi = reinterpret_cast<const char*>(fin);
   const char* const gi = reinterpret_cast<const char*>(gin);
   char* const fo = reinterpret_cast<char*>(fout);
@@ -1161,8 +1175,8 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
 #pragma unroll 1
   for (int p = 0; p < 3; ++p) dma_class<M, true>(lds, fin, gin, offf, offg, a, zb0 + p, (zb0 + p) % 3, slots);
   dma_class<M, false>(lds, fin, gin, offf, offg, a, z0, 0, slots);
-  R rf = *reinterpret_cast<const float*>(atb(opaque_base(fi + z0 * zsf), cxyf));
-  R rg = *reinterpret_cast<const float*>(atb(opaque_base(gi + z0 * zsg), cxyg));
+  R rf = Store<S>::ld(reinterpret_cast<const S*>(atb(opaque_base(fi + z0 * zsf), cxyf)));
+  R rg = Store<S>::ld(reinterpret_cast<const S*>(atb(opaque_base(gi + z0 * zsg), cxyg)));
   dma_wait();
   __syncthreads();
 
@@ -1198,13 +1212,13 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
       // 20 fewer VGPRs)
       int zero = 0;
       asm volatile("" : "+v"(zero));
-      ipull_all<M, UNI>(lds + zero, q, a, d, g, slots);
+      ipull_all<M, UNI>(lds + zero, q, a, lscale, d, g, slots);
     }
     // the rest populations of the next plane come straight to registers
     R nf = R(0), ng = R(0);
     if (more) {
-      nf = *reinterpret_cast<const float*>(atb(opaque_base(fi + (z + 1) * zsf), cxyf));
-      ng = *reinterpret_cast<const float*>(atb(opaque_base(gi + (z + 1) * zsg), cxyg));
+      nf = Store<S>::ld(reinterpret_cast<const S*>(atb(opaque_base(fi + (z + 1) * zsf), cxyf)));
+      ng = Store<S>::ld(reinterpret_cast<const S*>(atb(opaque_base(gi + (z + 1) * zsg), cxyg)));
     }
     __syncthreads();  // every pull of plane z has read the slots refilled next
     if (more) dma_class<M, false>(lds, fin, gin, offf, offg, a, z + 1, 0, slots);
@@ -1214,12 +1228,15 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const float* __restrict
       collide<3>(d, g, a.k, m);
       char* const fz = opaque_base(fo + z * zsf);
       char* const gz = opaque_base(go + z * zsg);
+      // rounding bits keyed by the node (its index in a row-pitched mesh), as in step_kernel
+      const unsigned h0 =
+          Store<S>::kDither ? mix32(unsigned(((long long)z * a.n[1] + q.g[1]) * a.pitch + q.g[0]) ^ dkey) : 0u;
 #pragma unroll
       for (int i = 0; i < LF::Q; ++i)
-        store_pop<S, NTS>(reinterpret_cast<float*>(atb(fz + i * ps4, cxyf)), d[i], 0u, i);
+        store_pop<S, NTS>(reinterpret_cast<S*>(atb(fz + i * ps4, cxyf)), d[i], h0, i);
 #pragma unroll
       for (int i = 0; i < LG::Q; ++i)
-        store_pop<S, NTS>(reinterpret_cast<float*>(atb(gz + i * ps4, cxyg)), g[i], 0u, 32 + i);
+        store_pop<S, NTS>(reinterpret_cast<S*>(atb(gz + i * ps4, cxyg)), g[i], h0, 32 + i);
     }
     rf = nf;
     rg = ng;
@@ -1318,11 +1335,11 @@ static hipError_t dispatch_step(const DevState& s, const void* fin, const void* 
                 : launch_step_t<D, S, LARGE, false, false, false>(s, fin, gin, fout, gout, partials, st);
 }
 
-// 3-D meshes with collision and FP32 storage use the marching kernel for
-// their plain launches (FP16 / BF16 storage keeps the tile kernel, whose
-// 2-byte tiles with paired staging and, for FP16, half-precision LDS suit
-// those types better).  64 x 8 columns, 32 planes per segment, one 512-thread workgroup per CU
-// (110 KB of LDS).  Measured on 256^3 / 384^3 tanh meshes (MLUPS; FETCH_SIZE
+// 3-D meshes with collision use the marching kernel for their plain launches
+// with FP32 storage, and with FP16 storage on uniform meshes (below); BF16
+// and the FP64-arithmetic modes keep the tile kernel.  64 x 8 columns, 32
+// planes per segment, one 512-thread workgroup per CU (110 KB of LDS for
+// FP32).  Measured on 256^3 / 384^3 tanh meshes (MLUPS; FETCH_SIZE
 // over the algorithmic reads on 256^3): 64 x 8 x 32 22.9k / 22.6k, 1.04x;
 // 32 x 8 x 32 20.6k / 22.1k, 1.32x; 32 x 16 x 32 20.6k / 21.3k, 1.14x;
 // 32 x 8 x 64 19.9k / 21.5k; 32 x 4 x 32 20.3k / 21.9k.  Wider rows leave
@@ -1336,27 +1353,39 @@ static int imarch_grid(const DevState& s, int* tiles) {
   return tiles[0] * tiles[1] * tiles[2];
 }
 
+// FP16 storage marches on uniform meshes only: its interpolating form needs
+// 220 VGPRs (2 waves per SIMD, against 8 for the FP16 tile kernel) and ran
+// 23.6k / 24.0k MLUPS on 256^3 / 384^3 tanh meshes against 30.6k / 31.0k for
+// the tile kernel, while the shift form runs 36.7k / 38.5k against
+// 31.3k / 32.4k on uniform meshes (raw half pairs staged into half-precision
+// LDS, as the FP16 tile kernel keeps them).
 static bool use_imarch(const DevState& s) {
-  return s.dim == 3 && s.storage == 0 && s.collide != 0;
+  return s.dim == 3 && s.collide != 0 && (s.storage == 0 || (s.storage == 2 && s.uniform != 0));
 }
 
 // Plain launches only: the statistics of the reducing launch would hold 13
 // FP64 accumulators across the march and push it beyond 256 VGPRs, so that
 // launch stays with step_kernel (once per call).
-template <bool LARGE>
+template <typename S>
+using IMarchFor = std::conditional_t<sizeof(S) == 2, March<IMarch3::TX, IMarch3::TY, IMarch3::ZS, 4>, IMarch3>;
+
+template <typename S, bool LARGE>
 static hipError_t launch_imarch(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
                                 hipStream_t st) {
+  using M = IMarchFor<S>;
   KArgs<float> a = make_args<float>(s);
   const int nb = imarch_grid(s, a.tiles);
   a.nblocks = nb;
   if (s.uniform)
-    hipLaunchKernelGGL((imarch3d_kernel<IMarch3, true, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
-                       static_cast<const float*>(fin), static_cast<const float*>(gin), static_cast<float*>(fout),
-                       static_cast<float*>(gout), a);
+    hipLaunchKernelGGL((imarch3d_kernel<M, S, true, LARGE>), dim3(nb), dim3(M::NT), 0, st,
+                       static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
+                       static_cast<S*>(gout), a);
+  else if constexpr (sizeof(S) == 4)
+    hipLaunchKernelGGL((imarch3d_kernel<M, S, false, LARGE>), dim3(nb), dim3(M::NT), 0, st,
+                       static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
+                       static_cast<S*>(gout), a);
   else
-    hipLaunchKernelGGL((imarch3d_kernel<IMarch3, false, LARGE>), dim3(nb), dim3(IMarch3::NT), 0, st,
-                       static_cast<const float*>(fin), static_cast<const float*>(gin), static_cast<float*>(fout),
-                       static_cast<float*>(gout), a);
+    return hipErrorInvalidValue;  // not dispatched: use_imarch takes FP16 on uniform meshes only
   return hipGetLastError();
 }
 
@@ -1407,10 +1436,10 @@ hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void
       return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
                         : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
     } else {
-      if constexpr (std::is_same_v<S, float>)
+      if constexpr (std::is_same_v<S, float> || std::is_same_v<S, __half>)
         if (use_imarch(s) && !reduce)
-          return s.large ? launch_imarch<true>(s, fin, gin, fout, gout, st)
-                         : launch_imarch<false>(s, fin, gin, fout, gout, st);
+          return s.large ? launch_imarch<S, true>(s, fin, gin, fout, gout, st)
+                         : launch_imarch<S, false>(s, fin, gin, fout, gout, st);
       if (s.dim == 3)
         return s.large ? dispatch_step<3, S, true>(s, fin, gin, fout, gout, reduce, partials, st)
                        : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
