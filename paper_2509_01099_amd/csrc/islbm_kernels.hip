@@ -84,9 +84,13 @@ struct Store<__half> {
   }
   __device__ static void st(__half* p, float v) { *p = __float2half_rn(v * kScale); }
   __device__ static void st_nt(__half* p, float v) { st(p, v); }
+  // the convert writes the low half of its destination and keeps the high
+  // half, which is never stored: seeding it with the input's own bits lets
+  // the destination reuse the input register (no copy per store)
   __device__ static void st_dither(__half* p, float v, unsigned bits) {
-    f16x2_t h = {0, 0};
-    h = __builtin_amdgcn_cvt_sr_f16_f32(h, v * kScale, bits, false);
+    const float x = v * kScale;
+    f16x2_t h = __builtin_bit_cast(f16x2_t, x);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, x, bits, false);
     *reinterpret_cast<__fp16*>(p) = h.x;
   }
 };
@@ -103,7 +107,7 @@ struct Store<__hip_bfloat16> {
   __device__ static void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
   __device__ static void st_nt(__hip_bfloat16* p, float v) { st(p, v); }
   __device__ static void st_dither(__hip_bfloat16* p, float v, unsigned bits) {
-    bf16x2_t h = {0, 0};
+    bf16x2_t h = __builtin_bit_cast(bf16x2_t, v);  // high half unused, as for FP16
     h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, bits, false);
     *reinterpret_cast<__bf16*>(p) = h.x;
   }
@@ -942,13 +946,17 @@ __device__ __forceinline__ void mplan(unsigned* offf, unsigned* offg, const KArg
 // hoists base + offset out of the z loop as one 64-bit vector address per
 // population and load unit, far more registers than the march can hold.
 // (The value must be the same in every lane: it is read from the first
-// active one.)
+// active one.)  The rebuilt pointer is marked as global memory, so that its
+// loads and stores stay global ones (scalar base + 32-bit vector offset)
+// rather than flat ones with a 64-bit vector address each.
 template <typename P>
 __device__ __forceinline__ P opaque_base(P p) {
   const unsigned long long v = reinterpret_cast<unsigned long long>(p);
   const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(v));
   const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
-  return reinterpret_cast<P>((static_cast<unsigned long long>(hi) << 32) | lo);
+  using G = __attribute__((address_space(1))) char*;
+  const G g = reinterpret_cast<G>((static_cast<unsigned long long>(hi) << 32) | lo);
+  return (P)((char*)g);
 }
 
 typedef __attribute__((address_space(4))) const float CFloat;  // constant (scalar-cache) memory
@@ -1159,7 +1167,7 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const S* __restrict__ f
   // offset, so no per-population 64-bit address stays live across the march
   const unsigned gy0 = in ? unsigned(q.g[1]) : 0u, gx0 = in ? unsigned(q.g[0]) : 0u;
   constexpr unsigned SB = sizeof(S);
-  const unsigned cxyf = (__umul24(gy0, unsigned(a.rsf)) + gx0) * SB, cxyg = (__umul24(gy0, unsigned(a.rsg)) + gx0) * SB;
+  unsigned cxyf = (__umul24(gy0, unsigned(a.rsf)) + gx0) * SB, cxyg = (__umul24(gy0, unsigned(a.rsg)) + gx0) * SB;
   const long long zsf = (long long)a.n[1] * a.rsf * SB, zsg = (long long)a.n[1] * a.rsg * SB;
   const long long ps4 = (long long)a.ps * SB;
   const char* const fi = reinterpret_cast<const char*>(fin);
@@ -1186,6 +1194,12 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const S* __restrict__ f
     const int zb = clampi(z - 1, 0, nz - 3);
     const int zbn = clampi(z, 0, nz - 3);
     const bool newz = more && zbn > zb;
+    // the 32-bit in-plane offsets are redefined (unchanged) each plane, so
+    // that their 64-bit extensions are not hoisted out of the loop: every
+    // access then keeps the scalar-base + 32-bit-offset form
+    asm volatile("" : "+v"(cxyf), "+v"(cxyg));
+#pragma unroll
+    for (int k = 0; k < MShapes<M>::total; ++k) asm volatile("" : "+v"(offf[k]), "+v"(offg[k]));
     R d[LF::Q], g[LG::Q];
     // z weights of the plane: uniform, read through the scalar cache (a
     // vector load here would make its wait also wait for the previous
@@ -1346,19 +1360,23 @@ static hipError_t dispatch_step(const DevState& s, const void* fin, const void* 
 // fewer x-halo cache lines and y-halo rows to fetch beyond L2.
 using IMarch3 = March<64, 8, 32>;
 
+template <class M>
 static int imarch_grid(const DevState& s, int* tiles) {
-  tiles[0] = (s.n[0] + IMarch3::TX - 1) / IMarch3::TX;
-  tiles[1] = (s.n[1] + IMarch3::TY - 1) / IMarch3::TY;
-  tiles[2] = (s.n[2] + IMarch3::ZS - 1) / IMarch3::ZS;
+  tiles[0] = (s.n[0] + M::TX - 1) / M::TX;
+  tiles[1] = (s.n[1] + M::TY - 1) / M::TY;
+  tiles[2] = (s.n[2] + M::ZS - 1) / M::ZS;
   return tiles[0] * tiles[1] * tiles[2];
 }
 
-// FP16 storage marches on uniform meshes only: its interpolating form needs
-// 220 VGPRs (2 waves per SIMD, against 8 for the FP16 tile kernel) and ran
-// 23.6k / 24.0k MLUPS on 256^3 / 384^3 tanh meshes against 30.6k / 31.0k for
-// the tile kernel, while the shift form runs 36.7k / 38.5k against
-// 31.3k / 32.4k on uniform meshes (raw half pairs staged into half-precision
-// LDS, as the FP16 tile kernel keeps them).
+// FP16 storage marches on uniform meshes only, in 64 x 4 columns (raw half
+// pairs staged into half-precision LDS, as the FP16 tile kernel keeps them;
+// 30 KB of LDS and about 80 VGPRs, five workgroups per CU): 38.2k / 42.5k
+// MLUPS on 256^3 / 384^3 against 36.7k / 39.1k in 64 x 8 columns and
+// 31.3k / 32.4k for the tile kernel.  Its interpolating form ran 30.7k /
+// 31.7k on tanh meshes in 64 x 8 columns (107 VGPRs once the pulls were
+// fenced in groups of slots, 220 without) and 16.4k / 17.3k in 64 x 4,
+// against 30.6k / 31.1k for the tile kernel, which stretched FP16 meshes
+// keep.
 static bool use_imarch(const DevState& s) {
   return s.dim == 3 && s.collide != 0 && (s.storage == 0 || (s.storage == 2 && s.uniform != 0));
 }
@@ -1367,14 +1385,14 @@ static bool use_imarch(const DevState& s) {
 // FP64 accumulators across the march and push it beyond 256 VGPRs, so that
 // launch stays with step_kernel (once per call).
 template <typename S>
-using IMarchFor = std::conditional_t<sizeof(S) == 2, March<IMarch3::TX, IMarch3::TY, IMarch3::ZS, 4>, IMarch3>;
+using IMarchFor = std::conditional_t<sizeof(S) == 2, March<64, 4, 32, 4>, IMarch3>;
 
 template <typename S, bool LARGE>
 static hipError_t launch_imarch(const DevState& s, const void* fin, const void* gin, void* fout, void* gout,
                                 hipStream_t st) {
   using M = IMarchFor<S>;
   KArgs<float> a = make_args<float>(s);
-  const int nb = imarch_grid(s, a.tiles);
+  const int nb = imarch_grid<M>(s, a.tiles);
   a.nblocks = nb;
   if (s.uniform)
     hipLaunchKernelGGL((imarch3d_kernel<M, S, true, LARGE>), dim3(nb), dim3(M::NT), 0, st,

@@ -26,11 +26,13 @@ def bars(storage):
 
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
-@pytest.mark.parametrize("dim,kind", [(2, "tanh"), (3, "tanh"), (3, "uniform")])
-def test_reduced_storage_vs_oracle(storage, dim, kind):
+@pytest.mark.parametrize("dim,kind,nz", [(2, "tanh", 0), (3, "tanh", 18), (3, "uniform", 18), (3, "uniform", 40)])
+def test_reduced_storage_vs_oracle(storage, dim, kind, nz):
+    """nz = 40 takes the 3-D march across a z-segment boundary (32 planes),
+    with columns cut short in x (70) and y (37)."""
     oracle.set_threads(16)
     a = 0 if kind == "uniform" else 1.5
-    meshes = [(kind, 70, a), (kind, 37, a), (kind, 18, a)][:dim]
+    meshes = [(kind, 70, a), (kind, 37, a), (kind, nz, a)][:dim]
     cav, orc = make_pair(meshes, 1e6 if dim == 2 else 1e7, 0.71, storage=storage)
     _, w, _ = oracle.lattice(dim, 0)
     f = random_populations(orc.shape, w, 0.05, seed=21)
@@ -47,7 +49,7 @@ def test_reduced_storage_vs_oracle(storage, dim, kind):
     fb, gb, sb = bars(storage)
     errs = {k: abs(st[k] - ost[k]) / max(abs(ost[k]), 1.0) for k in ("nu_hot", "nu_cold")}
     errs["re_vol"] = abs(st["re_vol"] - ost["re_vol"]) / abs(ost["re_vol"])
-    print(f"{storage} {dim}d {kind}: f {ef:.2e} g {eg:.2e} " +
+    print(f"{storage} {dim}d {kind} nz {nz}: f {ef:.2e} g {eg:.2e} " +
           " ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
     assert ef < fb and eg < gb
     assert all(v < sb for v in errs.values())
