@@ -110,7 +110,8 @@ HBM_ROWS = (("2-D 4096^2 cosine, Ra 1e8", "cosine", (4096, 4096), "fp32", 300),
             ("3-D 384^3 tanh, Ra 1e7", "tanh", (384, 384, 384), "fp32", 100),
             ("3-D 384^3 uniform, Ra 1e7", "uniform", (384, 384, 384), "fp32", 100),
             ("3-D 384^3 tanh, Ra 1e7", "tanh", (384, 384, 384), "fp16", 100),
-            ("3-D 384^3 tanh, Ra 1e7", "tanh", (384, 384, 384), "bf16", 100))
+            ("3-D 384^3 tanh, Ra 1e7", "tanh", (384, 384, 384), "bf16", 100),
+            ("3-D 384^3 uniform, Ra 1e7", "uniform", (384, 384, 384), "fp16", 100))
 
 
 def step_row(label, kind, shape, storage, steps, warmup=10, copy_GBs=None, Ra=None):
@@ -572,9 +573,10 @@ def throughput_table() -> dict:
     cases.append(("uniform", (4096, 4096), "fp32", 300))
     cases += [("tanh", (256, 256, 256), st, k) for st, k in
               (("fp32", 300), ("fp64", 150), ("fp32sr", 200), ("fp16", 300))]
-    cases.append(("uniform", (256, 256, 256), "fp32", 300))
+    cases += [("uniform", (256, 256, 256), st, k) for st, k in (("fp32", 300), ("fp16", 300), ("bf16", 300))]
     cases += [("tanh", (384, 384, 384), st, k) for st, k in
               (("fp32", 100), ("fp64", 50), ("fp32sr", 60), ("fp16", 100), ("bf16", 100))]
+    cases += [("uniform", (384, 384, 384), st, k) for st, k in (("fp32", 100), ("fp16", 100), ("bf16", 100))]
     rows = []
     for kind, shape, st, steps in cases:
         three = len(shape) == 3
