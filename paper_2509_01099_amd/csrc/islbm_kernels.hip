@@ -929,7 +929,7 @@ __device__ __forceinline__ void mplan(unsigned* offf, unsigned* offg, const KArg
 }
 
 // ---------------------------------------------------------------------------
-// 3-D marching kernel (plain launches; FP32 storage, and FP16 storage on
+// 3-D marching kernel (plain launches; FP32 storage, and 2-byte storage on
 // uniform meshes): the column and plane ring above, with the interpolated
 // pulls of step_kernel (or, on a uniform mesh, the shift by one node).
 // The ring already holds the three stencil planes zb .. zb + 2 of plane z
@@ -1111,7 +1111,9 @@ __global__ void __launch_bounds__(M::NT) imarch3d_kernel(const S* __restrict__ f
                                                          KArgs<float> a) {
   using R = float;
   static_assert(std::is_same_v<typename Store<S>::R, float>, "FP32 arithmetic");
-  using L = typename Lds<3, S>::type;  // float, or the raw scaled halves of FP16 storage
+  // LDS holds the stored values unchanged: float, or the raw 2-byte values
+  // (FP16 scaled by 2^12, BF16 unscaled), converted at each pull
+  using L = std::conditional_t<sizeof(S) == 2, S, typename Store<S>::R>;
   static_assert(sizeof(L) == sizeof(S), "the plane loads copy stored values into LDS unchanged");
   static_assert((M::U == 2) == (sizeof(S) == 2), "2-byte storage is staged in x pairs");
   const R lscale = Lds<3, S>::kScaled ? R(1.0 / 4096.0) : R(1);
@@ -1350,8 +1352,8 @@ static hipError_t dispatch_step(const DevState& s, const void* fin, const void* 
 }
 
 // 3-D meshes with collision use the marching kernel for their plain launches
-// with FP32 storage, and with FP16 storage on uniform meshes (below); BF16
-// and the FP64-arithmetic modes keep the tile kernel.  64 x 8 columns, 32
+// with FP32 storage, and with FP16 or BF16 storage on uniform meshes (below);
+// the FP64-arithmetic modes keep the tile kernel.  64 x 8 columns, 32
 // planes per segment, one 512-thread workgroup per CU (110 KB of LDS for
 // FP32).  Measured on 256^3 / 384^3 tanh meshes (MLUPS; FETCH_SIZE
 // over the algorithmic reads on 256^3): 64 x 8 x 32 22.9k / 22.6k, 1.04x;
@@ -1368,17 +1370,17 @@ static int imarch_grid(const DevState& s, int* tiles) {
   return tiles[0] * tiles[1] * tiles[2];
 }
 
-// FP16 storage marches on uniform meshes only, in 64 x 4 columns (raw half
-// pairs staged into half-precision LDS, as the FP16 tile kernel keeps them;
-// 30 KB of LDS and about 80 VGPRs, five workgroups per CU): 38.2k / 42.5k
-// MLUPS on 256^3 / 384^3 against 36.7k / 39.1k in 64 x 8 columns and
-// 31.3k / 32.4k for the tile kernel.  Its interpolating form ran 30.7k /
-// 31.7k on tanh meshes in 64 x 8 columns (107 VGPRs once the pulls were
-// fenced in groups of slots, 220 without) and 16.4k / 17.3k in 64 x 4,
-// against 30.6k / 31.1k for the tile kernel, which stretched FP16 meshes
-// keep.
+// 2-byte storage marches on uniform meshes only, in 64 x 4 columns (raw
+// stored pairs staged into 2-byte LDS; 30 KB of LDS and about 80 VGPRs, five
+// workgroups per CU).  FP16: 38.2k / 42.5k MLUPS on 256^3 / 384^3 against
+// 36.7k / 39.1k in 64 x 8 columns and 31.3k / 32.4k for the tile kernel;
+// BF16: 38.2k / 42.9k against 28.8k / 29.2k (the tile kernel keeps BF16 in
+// float LDS tiles).  The interpolating FP16 form ran 30.7k / 31.7k on tanh
+// meshes in 64 x 8 columns (107 VGPRs once the pulls were fenced in groups
+// of slots, 220 without) and 16.4k / 17.3k in 64 x 4, against 30.6k / 31.1k
+// for the tile kernel, which stretched 2-byte meshes keep.
 static bool use_imarch(const DevState& s) {
-  return s.dim == 3 && s.collide != 0 && (s.storage == 0 || (s.storage == 2 && s.uniform != 0));
+  return s.dim == 3 && s.collide != 0 && (s.storage == 0 || ((s.storage == 2 || s.storage == 3) && s.uniform != 0));
 }
 
 // Plain launches only: the statistics of the reducing launch would hold 13
@@ -1403,7 +1405,7 @@ static hipError_t launch_imarch(const DevState& s, const void* fin, const void* 
                        static_cast<const S*>(fin), static_cast<const S*>(gin), static_cast<S*>(fout),
                        static_cast<S*>(gout), a);
   else
-    return hipErrorInvalidValue;  // not dispatched: use_imarch takes FP16 on uniform meshes only
+    return hipErrorInvalidValue;  // not dispatched: use_imarch takes 2-byte storage on uniform meshes only
   return hipGetLastError();
 }
 
@@ -1454,7 +1456,7 @@ hipError_t launch_step(const DevState& s, const void* fin, const void* gin, void
       return s.dim == 2 ? dispatch_step<2, S, false>(s, fin, gin, fout, gout, reduce, partials, st)
                         : dispatch_step<3, S, false>(s, fin, gin, fout, gout, reduce, partials, st);
     } else {
-      if constexpr (std::is_same_v<S, float> || std::is_same_v<S, __half>)
+      if constexpr (std::is_same_v<S, float> || std::is_same_v<S, __half> || std::is_same_v<S, __hip_bfloat16>)
         if (use_imarch(s) && !reduce)
           return s.large ? launch_imarch<S, true>(s, fin, gin, fout, gout, st)
                          : launch_imarch<S, false>(s, fin, gin, fout, gout, st);
