@@ -355,14 +355,15 @@ struct Shapes {
   static constexpr int total = roff(SL::N);
 };
 
-// Element type of the LDS tiles.  In 3-D, FP16 storage keeps its raw
-// (scaled) halves in LDS: half the LDS of an FP32 tile, so four workgroups
-// fit a CU instead of two, and no conversion at the commit; the pulls read a
-// half and a float weight in one mixed-precision FMA and scale the
-// interpolated value once (kInv).  Measured: +18 % on 384^3; in 2-D, where
-// LDS does not limit the occupancy, the 16-bit LDS reads cost 10 % on
-// 1024^2, so 2-D tiles and every other storage type keep the arithmetic
-// type in LDS.
+// Element type of the LDS tiles.  In 3-D, 2-byte storage keeps its raw
+// stored values in LDS (FP16 halves scaled by 2^12, BF16 unscaled): half the
+// LDS of an FP32 tile, so four workgroups fit a CU instead of two, and no
+// conversion at the commit; the FP16 pulls read a half and a float weight in
+// one mixed-precision FMA and scale the interpolated value once, the BF16
+// pulls widen each tap by a shift (exact, so the results are unchanged).
+// Measured on 384^3: FP16 +18 %, BF16 +7.5 %; in 2-D, where LDS does not
+// limit the occupancy, the 16-bit LDS reads cost 10 % on 1024^2, so 2-D
+// tiles and every other storage type keep the arithmetic type in LDS.
 template <int D, typename S>
 struct Lds {
   using type = typename Store<S>::R;
@@ -372,6 +373,11 @@ template <>
 struct Lds<3, __half> {
   using type = __half;
   static constexpr bool kScaled = true;
+};
+template <>
+struct Lds<3, __hip_bfloat16> {
+  using type = __hip_bfloat16;
+  static constexpr bool kScaled = false;
 };
 template <typename R, typename L>
 __device__ __forceinline__ R lv(L v) {
@@ -462,7 +468,7 @@ __device__ __forceinline__ void commit_slot(L* lds, const W* regs) {
   for (int k = 0; k < SH::iters(m); ++k) {
     const int idx = threadIdx.x + k * T::NT;
     if (V % T::NT == 0 || k + 1 < SH::iters(m) || idx < V) {
-      if constexpr (std::is_same_v<L, __half>) {
+      if constexpr (sizeof(L) == 2) {
         reinterpret_cast<unsigned*>(dst)[idx] = regs[SH::roff(s) + k];  // the raw pair
       } else if constexpr (T::XH == 4) {
         L lo, hi;
@@ -975,7 +981,7 @@ struct IGeo {
   int ringdep[2];   // uniform mesh: ring slot of plane z - 1 (+1) and z + 1 (-1), clamped
 };
 
-// L: the LDS element type (float, or the raw scaled halves of FP16 storage,
+// L: the LDS element type (float, or the raw stored values of 2-byte storage,
 // read through lv / lw as in step_kernel; the caller applies the scale)
 template <class M, int s, bool UNI, typename L>
 __device__ __forceinline__ float ipull_slot(const L* lds, const IGeo& q) {
@@ -1374,7 +1380,7 @@ static int imarch_grid(const DevState& s, int* tiles) {
 // stored pairs staged into 2-byte LDS; 30 KB of LDS and about 80 VGPRs, five
 // workgroups per CU).  FP16: 38.2k / 42.5k MLUPS on 256^3 / 384^3 against
 // 36.7k / 39.1k in 64 x 8 columns and 31.3k / 32.4k for the tile kernel;
-// BF16: 38.2k / 42.9k against 28.8k / 29.2k (the tile kernel keeps BF16 in
+// BF16: 38.2k / 42.9k against 28.8k / 29.2k for the tile kernel (then with
 // float LDS tiles).  The interpolating FP16 form ran 30.7k / 31.7k on tanh
 // meshes in 64 x 8 columns (107 VGPRs once the pulls were fenced in groups
 // of slots, 220 without) and 16.4k / 17.3k in 64 x 4, against 30.6k / 31.1k
