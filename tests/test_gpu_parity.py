@@ -126,19 +126,20 @@ def test_parity_3d_fp32_random(kind, seed):
     cav.close()
 
 
-@pytest.mark.parametrize("nz,seed", [(65, 7), (67, 8)])
-def test_parity_3d_fp32_uniform_random(nz, seed):
-    """Uniform 3-D mesh (plain-shift streaming, z-marching kernel): 36 x 20 x nz
+@pytest.mark.parametrize("nx,nz,seed", [(36, 65, 7), (36, 67, 8), (100, 67, 9)])
+def test_parity_3d_fp32_uniform_random(nx, nz, seed):
+    """Uniform 3-D mesh (plain-shift streaming, z-marching kernel): nx x 20 x nz
     is ragged in x and y, and nz = 65 / 67 leaves a last z segment of one /
-    three planes."""
+    three planes (32-plane segments of 64 x 8 columns for nx = 36; nx = 100
+    takes the 128 x 4 columns of 64 planes, one column cut short in x)."""
     oracle.set_threads(16)
-    cav, orc = make_pair([("uniform", 36, 0), ("uniform", 20, 0), ("uniform", nz, 0)], 1e7, 0.71)
+    cav, orc = make_pair([("uniform", nx, 0), ("uniform", 20, 0), ("uniform", nz, 0)], 1e7, 0.71)
     f, g = _random_state(orc, seed)
     cav.set_populations(f, g, post_collision=False)
     orc.set_state(f, g)
     cav.step(100)
     orc.run(100)
-    _compare(cav, orc, 1e-5, 1e-4, f"3d fp32 uniform nz={nz}")
+    _compare(cav, orc, 1e-5, 1e-4, f"3d fp32 uniform nx={nx} nz={nz}")
     cav.close()
 
 
