@@ -161,13 +161,15 @@ int islbm_create(islbm_ctx** out, int lattice, const int n[3],
  * bitwise the same either way.  Asynchronous. */
 int islbm_step(islbm_ctx* ctx, long long nsteps);
 
-/* Captures, without running anything, the HIP graphs that a following
+/* Captures, without running a step, the HIP graphs that a following
  * islbm_step(ctx, nsteps) from the current state would replay (the 64-step
  * batch graph and the graph of the remaining plain launches), so that call
- * issues only graph launches and the final, reducing launch.  Advances no
- * time level.  nsteps >= 0; ISLBM_EINVAL on a null context or negative
- * count, ISLBM_EDEVICE when a capture fails.  A no-op when options.no_graph
- * is set. */
+ * issues only graph launches and the final, reducing launch.  The first call
+ * on a context also launches an empty graph and waits for it, so that the
+ * runtime's one-time graph-launch set-up does not fall into the next step
+ * call.  Advances no time level.  nsteps >= 0; ISLBM_EINVAL on a null
+ * context or negative count, ISLBM_EDEVICE when a capture or the empty
+ * launch fails.  A no-op when options.no_graph is set. */
 int islbm_plan_steps(islbm_ctx* ctx, long long nsteps);
 
 /* Macroscopic fields at the current time level (pre-collision moments:

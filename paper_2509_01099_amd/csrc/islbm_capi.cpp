@@ -59,6 +59,7 @@ struct islbm_ctx {
   } tail[4];
   int tail_next = 0;
   long long tail_last = -1;  // key of the previous remainder left ungraphed
+  bool graph_warm = false;   // the empty warm-up graph has run on this context
   std::string err;
 };
 
@@ -662,6 +663,24 @@ extern "C" int islbm_plan_steps(islbm_ctx* ctx, long long nsteps) {
   if (plain >= kTailMin && !find_tail(ctx, plain, ctx->cur)) {
     hipError_t e = add_tail(ctx, plain, ctx->cur);
     if (e != hipSuccess) return hipfail(ctx, e, "graph capture");
+  }
+  // The runtime sets up its graph-launch path on the first launch in a
+  // process (measured: a 20-step call on 1024^2 took 418-454 us the first
+  // time against 385-392 us after).  An empty graph, launched once per
+  // context, does that set-up here instead; it runs no step.
+  if (!ctx->graph_warm) {
+    hipGraph_t g = nullptr;
+    hipGraphNode_t node;
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e == hipSuccess) e = hipGraphAddEmptyNode(&node, g, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(x, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hipfail(ctx, e, "graph warm-up");
+    ctx->graph_warm = true;
   }
   return ISLBM_OK;
 }
