@@ -1306,7 +1306,13 @@ static int grid_of(const DevState& s, int* tiles) {
 
 // 2-byte storage stages x pairs (Tile XH = 4) and in 2-D keeps the short
 // 64 x 4 tiles also for large meshes (measured 13 % faster there than 64 x 8
-// tiles with two rows per thread).
+// tiles with two rows per thread).  In 3-D its LDS tiles hold the raw 2-byte
+// values, and wide flat 64 x 2 x 2 tiles (256 threads, 27 KB of LDS) beat
+// the FP32 shape: FP16 32.8k / 34.2k MLUPS on 256^3 / 384^3 tanh meshes
+// against 30.3k / 31.2k in 32 x 4 x 4 (BF16 31.0k against 28.3k on 384^3;
+// 64 x 2 x 4 31.8k / 32.9k, 64 x 4 x 2 31.5k / 32.3k, 128 x 2 x 2 29.6k /
+// 31.0k, 32 x 4 x 2 28.8k / 29.4k); on the 400^3 erf mesh 30.3k against
+// 29.8k.
 template <class T>
 struct Paired;
 template <int TX, int TY, int TZ, int NR, int XH>
@@ -1325,6 +1331,15 @@ struct TileSel<2, __half, L> {
 template <bool L>
 struct TileSel<2, __hip_bfloat16, L> {
   using T = Tile<64, 4, 1, 1, 4>;
+};
+using Tile3Pair = Tile<64, 2, 2, 1, 4>;
+template <bool L>
+struct TileSel<3, __half, L> {
+  using T = Tile3Pair;
+};
+template <bool L>
+struct TileSel<3, __hip_bfloat16, L> {
+  using T = Tile3Pair;
 };
 
 template <int D, typename S, bool LARGE, bool UNI, bool RED, bool COL>
@@ -1458,6 +1473,10 @@ int step_blocks(const DevState& s) {
     return lg ? blocks_for<2, float, true>(s) : blocks_for<2, float, false>(s);
   }
   if (dbl) return blocks_for<3, double, false>(s);
+  if (s.storage == 2 || s.storage == 3) {
+    int tiles[3];
+    return grid_of<3, Tile3Pair>(s, tiles);
+  }
   return lg ? blocks_for<3, float, true>(s) : blocks_for<3, float, false>(s);
 }
 
